@@ -1,0 +1,242 @@
+/*
+ * tlt.h -- C ABI of the MI355X translucent-transport library (libtlt.so).
+ *
+ * Per-frame radiance of a translucent object under the dipole diffusion
+ * model with a PCA-factorised material function and Haar-compressed
+ * precomputed transport (Wang, Hua, Huo, Bao, "Real-time Rendering and
+ * Editing of Scattering Effects for Translucent Objects"):
+ *
+ *   E[q,i,ch]    = sum_lm T[i,lm] L[light(q),lm,ch]                 (Eq. 6)
+ *   Ehat[q,:,ch] = Haar(pad(A o E[q,:,ch]))  over Morton order      (Eq. 8)
+ *   g[m,ch,k]    = sum_n R_d(r_n; theta[m,ch]) b_k[n]     (Sec. 2.2, Eq. 4)
+ *   B[q,v,ch]    = sum_k g[mat(q),ch,k] sum_{j in S(o,k)} W_k[o,j] Ehat[q,j,ch]
+ *                  with v = perm[o]                (Eq. 7, 8; Sec. 4 Steps 1-4)
+ *
+ * Column convention: a launch renders n_out = max(n_light, n_mat) sets of
+ * three RGB channels; set q uses lighting light(q) = (n_light > 1 ? q : 0)
+ * and material mat(q) = (n_mat > 1 ? q : 0).  n_light and n_mat must be
+ * equal or one of them must be 1.
+ *
+ * Precision: a transport stored in F64 runs entirely in float64 (E, Ehat,
+ * accumulation, B, gradients).  Any other storage (F32, BF16, F16) runs in
+ * float32 with float32 accumulation; the material weights g are always
+ * evaluated in float64 on the GPU.
+ *
+ * Errors: every call returns a tlt_status; nothing aborts or throws across
+ * the ABI.  tlt_last_error() gives a message for the last failing call on a
+ * context (or, for ctx == NULL, on the calling thread).  GPU work is
+ * asynchronous on the caller's HIP stream: launch failures return
+ * TLT_E_HIP, faults inside kernels surface at a later synchronising call.
+ * A context is not thread-safe; use one per thread.
+ */
+#ifndef TLT_H
+#define TLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tlt_ctx tlt_ctx;
+
+typedef enum {
+  TLT_OK = 0,
+  TLT_W_MATERIAL_OUT_OF_RANGE = 1, /* warning: material outside the PCA table */
+  TLT_E_ARG = -1,                  /* bad argument, shape or value */
+  TLT_E_STATE = -2,                /* call out of order */
+  TLT_E_OOM = -3,                  /* device or host allocation failed */
+  TLT_E_HIP = -4,                  /* HIP runtime error */
+  TLT_E_FORMAT = -5                /* malformed transport (indices, sizes) */
+} tlt_status;
+
+enum { TLT_F64 = 0, TLT_F32 = 1, TLT_BF16 = 2, TLT_F16 = 3 };
+enum { TLT_WAVELET_NONE = 0, TLT_WAVELET_HAAR = 1 };
+enum {
+  TLT_SAVE_FOR_BACKWARD = 1, /* keep v_k[o,c] for render_backward */
+  TLT_FORCE_FULL = 2         /* recompute every stage, ignoring dirty flags */
+};
+
+/*
+ * Host-side geometry precompute (no GPU work).
+ *
+ * From a closed triangle mesh computes, all in float64:
+ *   - Morton order: perm[p] = vertex id at position p of the 1-D wavelet
+ *     domain; coordinates quantised to 21 bits over the bounding box,
+ *     bits interleaved x,y,z (x most significant), stable on equal keys
+ *     (replaces the flattened quadtrees of Sec. 3.1);
+ *   - per-vertex area A_i = 1/3 of the incident triangle areas (dA, Eq. 6);
+ *   - vertex normals (area-weighted face normals, normalised);
+ *   - SH transfer T[i,lm] = Ahat_l Y_lm(n_i) of the unshadowed clamped
+ *     cosine (E of Eq. 6 with visibility 1), real orthonormal SH without
+ *     the Condon-Shortley phase, index l*l+l+m;
+ *   - r nodes r_n = r_max (n/(n_r-1))^2 and the PCA basis b_k: the first K
+ *     right singular vectors of M[material][node] = R_d(r_node; material)
+ *     over the material grid (Eq. 5, Sec. 2.2), each signed so that its
+ *     entry of largest magnitude is positive.  Grid: sigma_a and sigma_s'
+ *     log-spaced over [lo,hi], eta linear, with n points each.
+ * All output arrays are caller-allocated host memory; arrays in Morton
+ * order are indexed by position p.  Errors: TLT_E_ARG for bad sizes or
+ * degenerate meshes (zero-area vertex, zero normal).
+ */
+typedef struct {
+  int32_t n_vertices;        /* N >= 2 */
+  int32_t n_faces;
+  const double *vertices;    /* [N][3], mm */
+  const int32_t *faces;      /* [n_faces][3], counter-clockwise from outside */
+  int32_t n_sh;              /* (lmax+1)^2 with lmax in 0..7 */
+  int32_t K;                 /* basis functions kept, 1..n_r */
+  int32_t n_r;               /* r nodes, 2..1024 (256 by default) */
+  double r_max;              /* >= every vertex-to-vertex distance, mm */
+  double mat_lo[3];          /* sigma_a, sigma_s' (1/mm), eta */
+  double mat_hi[3];
+  int32_t mat_n[3];          /* grid points per parameter, each >= 1 */
+  /* outputs */
+  int32_t *perm;             /* [N] */
+  double *position;          /* [N][3]   Morton order */
+  double *area;              /* [N]      Morton order */
+  double *normal;            /* [N][3]   Morton order */
+  double *transfer;          /* [N][n_sh] Morton order */
+  double *r_nodes;           /* [n_r] */
+  double *basis;             /* [K][n_r] */
+  double *singular_values;   /* [min(n_mat, n_r)] or NULL */
+} tlt_scene;
+
+tlt_status tlt_prepare_scene(tlt_scene *scene);
+
+/*
+ * Host-only: the float64 transport rows that load_transport builds when
+ * desc->col == NULL, for selected output points.  For each of the n_rows
+ * Morton positions rows[i] and each k < K, writes the n_keep kept (column,
+ * value) pairs of row (rows[i], k) to col_out/val_out [n_rows][K][n_keep],
+ * columns ascending (precompute Step 1 of Sec. 3.2; Eq. 7 and 8).
+ * position [N][3] Morton order; n_cols = n_pad (HAAR) or N (NONE).
+ * TLT_E_ARG for bad sizes or rows out of range.
+ */
+tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t n_r,
+                          int32_t wavelet, int64_t n_keep, const double *position,
+                          const double *r_nodes, const double *basis, int64_t n_rows,
+                          const int64_t *rows, int32_t *col_out, double *val_out);
+
+/*
+ * Transport description for load_transport.  Host pointers, caller-owned,
+ * read only during the call.
+ *
+ * Rows are ordered (o, k) with o the Morton position: row = o*K + k.  Each
+ * row holds n_keep (column, value) pairs with strictly ascending columns.
+ * With wavelet HAAR column j indexes the orthonormal Haar coefficient of
+ * the zero-padded Morton list (layout [s0, d0, d1[0..1], ...]; Eq. 8) and
+ * the row keeps the n_keep coefficients of largest magnitude (Sec. 3.2,
+ * precompute Step 1; ties to the lower j).  With wavelet NONE column j is
+ * the Morton position itself (the plain matrix of Eq. 7).  Row values are
+ * btilde_k(|x_o - x_j|): the basis b_k interpolated linearly between the
+ * r nodes, i.e. the area weight is applied to the irradiance side.
+ *
+ * col == NULL: the rows are computed here in float64 from `position`,
+ *   `r_nodes` and `basis` (n_keep <= n_cols), then stored in value_dtype.
+ * col != NULL: col/val are taken as given (val in value_dtype); every
+ *   column is checked to lie in [0, n_cols) and rows to ascend, else
+ *   TLT_E_FORMAT.
+ * n_cols = n_pad (HAAR, n_pad = next power of two >= N) or N (NONE).
+ * The library keeps its own device copies until tlt_destroy or the next
+ * load_transport.  Material and lighting state are reset.
+ */
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_pad;
+  int32_t n_sh;
+  int32_t K;
+  int32_t n_r;
+  int32_t wavelet;           /* TLT_WAVELET_* */
+  int32_t value_dtype;       /* storage of W: TLT_F64/F32/BF16/F16 */
+  int32_t transfer_dtype;    /* storage of T: same set; F64 iff value_dtype F64 */
+  int64_t n_keep;            /* entries per row, 1..n_cols */
+  const int32_t *col;        /* [N*K][n_keep] or NULL */
+  const void *val;           /* [N*K][n_keep] in value_dtype, or NULL */
+  const double *position;    /* [N][3] Morton order (needed when col == NULL) */
+  const double *transfer;    /* [N][n_sh] Morton order */
+  const double *area;        /* [N] Morton order */
+  const int32_t *perm;       /* [N] */
+  const double *r_nodes;     /* [n_r] */
+  const double *basis;       /* [K][n_r] */
+  const double *mat_range;   /* [3][2] (lo, hi) of the PCA table, or NULL */
+} tlt_transport_desc;
+
+tlt_status tlt_create(tlt_ctx **out, int hip_device);
+void tlt_destroy(tlt_ctx *ctx);
+const char *tlt_last_error(const tlt_ctx *ctx);
+
+/* Loads (or builds) the transport and uploads the geometry. Synchronous. */
+tlt_status load_transport(tlt_ctx *ctx, const tlt_transport_desc *desc);
+
+/*
+ * Material for the next render: theta_dev [n_mat][3 channels][sigma_a,
+ * sigma_s', eta] float64 in device memory, owned by the caller and read on
+ * `hip_stream` by render (it must stay valid until that render completes).
+ * Copies the values to the host once (synchronising the stream) to
+ * validate them: sigma_a > 0, sigma_s' > 0, eta >= 1, all finite, else
+ * TLT_E_ARG.  Values outside mat_range give TLT_W_MATERIAL_OUT_OF_RANGE but
+ * are accepted.  Marks the material weights dirty (Step 3 of Sec. 4).
+ */
+tlt_status set_material(tlt_ctx *ctx, int n_mat, const double *theta_dev,
+                        void *hip_stream);
+
+/*
+ * Lighting for the next render: sh_dev [n_light][n_sh][3] in device memory
+ * (float64 for an F64 transport, else float32), read by render on its
+ * stream.  Records the pointer only; marks the irradiance dirty.
+ */
+tlt_status set_lighting(tlt_ctx *ctx, int n_light, const void *sh_dev);
+
+/*
+ * Renders B [n_out][N][3] (original vertex order, float64 for an F64
+ * transport else float32) into caller-owned device memory on hip_stream.
+ * Recomputes only what changed since the last render (a material change
+ * reruns Steps 3-4 of Sec. 4 only) unless TLT_FORCE_FULL.  With
+ * TLT_SAVE_FOR_BACKWARD keeps v_k[o,c] for render_backward.
+ * TLT_E_STATE before load_transport / set_material / set_lighting.
+ */
+tlt_status render(tlt_ctx *ctx, void *B_dev, void *hip_stream, int flags);
+
+/*
+ * Adjoint of the last render (which must have used TLT_SAVE_FOR_BACKWARD,
+ * else TLT_E_STATE).  dB_dev [n_out][N][3] upstream gradient (precision of
+ * B).  Writes dSH_dev [n_light][n_sh][3] (precision of B) and dTheta_dev
+ * [n_mat][3][3] float64, both device memory, overwritten (not accumulated).
+ * The lighting gradient is the exact transpose of the transport:
+ * sum_k g_k (W_k G)^T dB with G = Haar(pad(A o T)) precomputed at load.
+ */
+tlt_status render_backward(tlt_ctx *ctx, const void *dB_dev, void *dSH_dev,
+                           double *dTheta_dev, void *hip_stream);
+
+/*
+ * Diagnostics (host copies, synchronous).  tlt_read_rows copies rows
+ * (row = o*K + k) of the stored transport: columns as int32 and values
+ * widened to float64 (exactly the stored values).  tlt_read_state copies
+ * an internal buffer: 0 = Ehat [n_pad or N][C_stride] (compute precision),
+ * 1 = g [n_mat][3][K] float64, 2 = dg/dtheta [n_mat][3][K][3] float64;
+ * *bytes receives the size when out == NULL.
+ */
+tlt_status tlt_read_rows(tlt_ctx *ctx, int64_t n_rows, const int64_t *rows,
+                         int32_t *col_out, double *val_out);
+tlt_status tlt_read_state(tlt_ctx *ctx, int which, void *out, size_t *bytes,
+                          int *c_stride);
+
+/*
+ * Tile choice of the transport kernel: each lane accumulates
+ * `columns_per_lane` consecutive output columns (one of 4, 8, 12, 16, 24,
+ * 28, 32, 36, 48, 64); 0 restores the built-in choice (the smallest that
+ * covers all columns, else 48-column slices).  Used by the autotuner.
+ * Takes effect at the next render; TLT_E_ARG for unsupported values.
+ */
+tlt_status tlt_set_tile(tlt_ctx *ctx, int columns_per_lane);
+int tlt_get_tile(const tlt_ctx *ctx);
+
+/* Library version string (static storage). */
+const char *tlt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TLT_H */

@@ -1,0 +1,27 @@
+"""torch.autograd.Function over the library's render and render_backward."""
+from __future__ import annotations
+
+import torch
+
+
+class TranslucentRender(torch.autograd.Function):
+    """B = render(sh, theta) on a loaded Renderer; gradients w.r.t. the SH
+    lighting and the per-channel (sigma_a, sigma_s', eta) come from the
+    library's adjoint kernels."""
+
+    @staticmethod
+    def forward(ctx, renderer, sh, theta):
+        renderer.set_lighting(sh.detach().contiguous())
+        renderer.set_material(theta.detach().contiguous())
+        B = renderer.render(save=True)
+        ctx.renderer = renderer
+        return B
+
+    @staticmethod
+    def backward(ctx, dB):
+        dSH, dTheta = ctx.renderer.render_backward(dB.contiguous())
+        return None, dSH, dTheta
+
+
+def render(renderer, sh, theta):
+    return TranslucentRender.apply(renderer, sh, theta)

@@ -1,0 +1,598 @@
+// C ABI of libtlt.so: context, transport loading, per-frame render and its
+// adjoint.  See include/tlt.h for the contract of every entry point.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/tlt.h"
+#include "host_internal.h"
+#include "kernels.h"
+
+using namespace tlt;
+
+struct tlt_ctx {
+  int device = 0;
+  std::string err;
+
+  // transport
+  bool loaded = false;
+  int N = 0, n_pad = 0, n_sh = 0, n_shp = 0, K = 0, nr = 0, wavelet = 0, vdt = 0, tdt = 0;
+  int64_t n_keep = 0;
+  int n_rows = 0;  // rows of Ehat: n_pad (Haar) or N (plain)
+  bool fp64 = false;
+  size_t esz = 4;
+  int32_t *col = nullptr;
+  void *val = nullptr;
+  void *T = nullptr;
+  void *area = nullptr;
+  int32_t *perm = nullptr;
+  double *rn = nullptr, *basis = nullptr;
+  double mat_range[6] = {0, 0, 0, 0, 0, 0};
+  bool has_range = false;
+
+  // lighting-transfer product for the adjoint: P[k][o][Psh] = W_k G
+  bool have_P = false;
+  int Psh = 0, Gs = 0;
+  void *P = nullptr;
+
+  // inputs of the next render
+  const void *sh = nullptr;
+  int n_light = 0;
+  const double *theta = nullptr;
+  int n_mat = 0;
+  bool mat_dirty = true, light_dirty = true;
+
+  // column-dependent buffers
+  int C = 0, Cs = 0, cpl = 0, n_out = 0, tile_req = 0;
+  int buf_nlight = -1, buf_nmat = -1;
+  void *Lm = nullptr, *ehat = nullptr, *partial = nullptr, *gcol = nullptr, *V = nullptr;
+  double *g64 = nullptr, *dg64 = nullptr;
+  void *adj = nullptr;
+  size_t adj_bytes = 0;
+  bool v_valid = false;   // V holds v_k of the current lighting
+};
+
+namespace {
+
+tlt_status hip_fail(tlt_ctx *c, hipError_t e, const char *what) {
+  return fail(c ? &c->err : nullptr, TLT_E_HIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPC(ctx, expr)                                   \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+  } while (0)
+
+template <typename T> void dfree(T *&p) {
+  if (p) (void)hipFree((void *)p);
+  p = nullptr;
+}
+
+tlt_status dalloc(tlt_ctx *c, void **p, size_t bytes, const char *what) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(&c->err, e == hipErrorOutOfMemory ? TLT_E_OOM : TLT_E_HIP,
+                std::string("allocating ") + what + " (" + std::to_string(bytes) +
+                    " bytes): " + hipGetErrorString(e));
+  }
+  return TLT_OK;
+}
+
+size_t dtype_size(int dt) { return dt == TLT_F64 ? 8 : dt == TLT_F32 ? 4 : 2; }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+const int kCpl[] = {4, 8, 12, 16, 24, 28, 32, 36, 48, 64};
+
+int auto_cpl(int C) {
+  for (int v : kCpl)
+    if (v >= C) return v;
+  return 48;
+}
+
+void free_columns(tlt_ctx *c) {
+  dfree(c->Lm);
+  dfree(c->ehat);
+  dfree(c->partial);
+  dfree(c->gcol);
+  dfree(c->V);
+  dfree(c->g64);
+  dfree(c->dg64);
+  dfree(c->adj);
+  c->adj_bytes = 0;
+  c->C = c->Cs = c->n_out = 0;
+  c->buf_nlight = c->buf_nmat = -1;
+  c->v_valid = false;
+}
+
+void free_all(tlt_ctx *c) {
+  free_columns(c);
+  dfree(c->col);
+  dfree(c->val);
+  dfree(c->T);
+  dfree(c->area);
+  dfree(c->perm);
+  dfree(c->rn);
+  dfree(c->basis);
+  dfree(c->P);
+  c->have_P = false;
+  c->loaded = false;
+  c->sh = nullptr;
+  c->theta = nullptr;
+  c->n_light = c->n_mat = 0;
+}
+
+int host_threads() {
+  const char *e = std::getenv("TLT_THREADS");
+  if (e && std::atoi(e) > 0) return std::atoi(e);
+  unsigned h = std::thread::hardware_concurrency();
+  if (h == 0) h = 4;
+  return (int)std::min<unsigned>(h, 16);
+}
+
+// (Re)allocates every buffer whose size depends on the column count.
+tlt_status ensure_columns(tlt_ctx *c) {
+  const int n_out = std::max(c->n_light, c->n_mat);
+  int cpl = c->tile_req ? c->tile_req : auto_cpl(3 * n_out);
+  if (c->buf_nlight == c->n_light && c->buf_nmat == c->n_mat && cpl == c->cpl && c->ehat)
+    return TLT_OK;
+  free_columns(c);
+  c->n_out = n_out;
+  c->C = 3 * n_out;
+  c->cpl = cpl;
+  const int chunks = (c->C + cpl - 1) / cpl;
+  c->Cs = round_up(std::max(c->C, chunks * cpl), 16);
+  const size_t e = c->esz;
+  tlt_status s;
+  if ((s = dalloc(c, &c->Lm, e * c->n_shp * c->Cs, "lighting matrix")) != TLT_OK) return s;
+  if ((s = dalloc(c, &c->ehat, e * (size_t)c->n_rows * c->Cs, "Ehat")) != TLT_OK) return s;
+  const int ch_rows = std::min(c->n_rows, 256);
+  const int n_chunks = (c->n_rows + ch_rows - 1) / ch_rows;
+  if ((s = dalloc(c, &c->partial, e * (size_t)n_chunks * c->Cs, "Haar partials")) != TLT_OK) return s;
+  if ((s = dalloc(c, &c->gcol, e * (size_t)c->K * c->Cs, "column weights")) != TLT_OK) return s;
+  HIPC(c, hipMemset(c->gcol, 0, e * (size_t)c->K * c->Cs));
+  if ((s = dalloc(c, (void **)&c->g64, sizeof(double) * c->n_mat * 3 * c->K, "g")) != TLT_OK) return s;
+  if ((s = dalloc(c, (void **)&c->dg64, sizeof(double) * c->n_mat * 9 * c->K, "dg")) != TLT_OK) return s;
+  c->buf_nlight = c->n_light;
+  c->buf_nmat = c->n_mat;
+  c->mat_dirty = c->light_dirty = true;
+  return TLT_OK;
+}
+
+tlt_status ensure_V(tlt_ctx *c) {
+  if (c->V) return TLT_OK;
+  return dalloc(c, &c->V, c->esz * (size_t)c->K * c->N * c->Cs, "saved v_k");
+}
+
+// G = Haar(pad(A o T)) and P = W G (per k), for the lighting gradient.
+tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
+  if (c->have_P) return TLT_OK;
+  int cplP = 0;
+  for (int v : kCpl)
+    if (v >= c->n_sh) { cplP = v; break; }
+  if (!cplP) return fail(&c->err, TLT_E_ARG, "n_sh too large for the adjoint");
+  c->Psh = cplP;
+  c->Gs = round_up(cplP, 16);
+  const size_t e = c->esz;
+  void *Lm = nullptr, *G = nullptr, *part = nullptr, *gz = nullptr;
+  tlt_status s;
+  const int ch_rows = std::min(c->n_rows, 256);
+  const int n_chunks = (c->n_rows + ch_rows - 1) / ch_rows;
+  Cols ident{c->Gs, c->Gs / 3, 1, 1};
+  if ((s = dalloc(c, &c->P, e * (size_t)c->K * c->N * c->Psh, "P")) != TLT_OK) return s;
+  if ((s = dalloc(c, &Lm, e * c->n_shp * c->Gs, "identity lighting")) != TLT_OK) goto out;
+  if ((s = dalloc(c, &G, e * (size_t)c->n_rows * c->Gs, "G")) != TLT_OK) goto out;
+  if ((s = dalloc(c, &part, e * (size_t)n_chunks * c->Gs, "G partials")) != TLT_OK) goto out;
+  if ((s = dalloc(c, &gz, e * (size_t)c->K * c->Gs, "zero weights")) != TLT_OK) goto out;
+  {
+    hipError_t he;
+    if ((he = hipMemsetAsync(gz, 0, e * (size_t)c->K * c->Gs, st)) != hipSuccess ||
+        (he = launch_lmat(nullptr, c->fp64, c->n_sh, c->n_shp, c->Gs, ident, Lm, st)) != hipSuccess ||
+        (he = launch_tl_haar(c->T, c->tdt, c->N, c->n_sh, c->n_shp, Lm, c->area, c->fp64,
+                             c->wavelet == TLT_WAVELET_HAAR, c->n_rows, c->Gs, G, part, st)) != hipSuccess ||
+        (he = launch_transport(c->col, c->val, c->vdt, c->n_keep, c->K, c->N, G, c->Gs, c->Psh,
+                               c->Psh, gz, c->perm, nullptr, c->P, c->Psh, c->fp64, st)) != hipSuccess ||
+        (he = hipStreamSynchronize(st)) != hipSuccess) {
+      s = hip_fail(c, he, "building the lighting-transfer product");
+      goto out;
+    }
+  }
+  c->have_P = true;
+  s = TLT_OK;
+out:
+  dfree(Lm);
+  dfree(G);
+  dfree(part);
+  dfree(gz);
+  return s;
+}
+
+float half_to_float(uint16_t h) {
+  const uint32_t sgn = (uint32_t)(h >> 15) << 31;
+  const int ex = (h >> 10) & 31;
+  uint32_t man = h & 1023;
+  uint32_t bits;
+  if (ex == 0) {
+    if (man == 0) {
+      bits = sgn;
+    } else {  // subnormal: value = man * 2^-24
+      float f = std::ldexp((float)man, -24);
+      return (h >> 15) ? -f : f;
+    }
+  } else if (ex == 31) {
+    bits = sgn | 0x7f800000u | (man << 13);
+  } else {
+    bits = sgn | ((uint32_t)(ex - 15 + 127) << 23) | (man << 13);
+  }
+  float f;
+  std::memcpy(&f, &bits, 4);
+  return f;
+}
+
+double widen(const void *p, int dt, size_t i) {
+  switch (dt) {
+    case TLT_F64: return ((const double *)p)[i];
+    case TLT_F32: return ((const float *)p)[i];
+    case TLT_BF16: {
+      uint32_t b = (uint32_t)((const uint16_t *)p)[i] << 16;
+      float f;
+      std::memcpy(&f, &b, 4);
+      return f;
+    }
+    default: return half_to_float(((const uint16_t *)p)[i]);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tlt_version(void) { return "tlt 0.1 gfx950"; }
+
+tlt_status tlt_create(tlt_ctx **out, int hip_device) {
+  if (!out) return fail(nullptr, TLT_E_ARG, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || n <= 0)
+    return fail(nullptr, TLT_E_HIP, std::string("no HIP device: ") + hipGetErrorString(e));
+  if (hip_device < 0 || hip_device >= n) return fail(nullptr, TLT_E_ARG, "device index out of range");
+  e = hipSetDevice(hip_device);
+  if (e != hipSuccess) return fail(nullptr, TLT_E_HIP, hipGetErrorString(e));
+  tlt_ctx *c = new (std::nothrow) tlt_ctx;
+  if (!c) return fail(nullptr, TLT_E_OOM, "context allocation");
+  c->device = hip_device;
+  *out = c;
+  return TLT_OK;
+}
+
+void tlt_destroy(tlt_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  free_all(c);
+  delete c;
+}
+
+const char *tlt_last_error(const tlt_ctx *c) {
+  return c ? c->err.c_str() : g_thread_error.c_str();
+}
+
+tlt_status tlt_set_tile(tlt_ctx *c, int cpl) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (cpl != 0 && !transport_cpl_supported(cpl, c->fp64))
+    return fail(&c->err, TLT_E_ARG, "unsupported columns_per_lane " + std::to_string(cpl));
+  c->tile_req = cpl;
+  return TLT_OK;
+}
+
+int tlt_get_tile(const tlt_ctx *c) { return c ? c->cpl : 0; }
+
+tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
+  if (!c || !d) return fail(c ? &c->err : nullptr, TLT_E_ARG, "NULL argument");
+  HIPC(c, hipSetDevice(c->device));
+  const int N = d->n_vertices;
+  if (N < 1) return fail(&c->err, TLT_E_ARG, "n_vertices must be >= 1");
+  if (d->wavelet != TLT_WAVELET_NONE && d->wavelet != TLT_WAVELET_HAAR)
+    return fail(&c->err, TLT_E_ARG, "unknown wavelet");
+  int n_pad = 1;
+  while (n_pad < N) n_pad <<= 1;
+  if (d->wavelet == TLT_WAVELET_HAAR && d->n_pad != n_pad)
+    return fail(&c->err, TLT_E_ARG, "n_pad must be the next power of two >= n_vertices");
+  if (d->wavelet == TLT_WAVELET_HAAR && n_pad > (1 << 19))
+    return fail(&c->err, TLT_E_ARG, "n_pad above 2^19 is not supported");
+  const int n_cols = d->wavelet == TLT_WAVELET_HAAR ? n_pad : N;
+  if (d->n_sh < 1 || d->n_sh > 64) return fail(&c->err, TLT_E_ARG, "n_sh must be in 1..64");
+  if (d->K < 1 || d->K > 64) return fail(&c->err, TLT_E_ARG, "K must be in 1..64");
+  if (d->n_r < 2 || d->n_r > 1024) return fail(&c->err, TLT_E_ARG, "n_r must be in 2..1024");
+  if (d->n_keep < 1 || d->n_keep > n_cols) return fail(&c->err, TLT_E_ARG, "n_keep out of range");
+  for (int dt : {d->value_dtype, d->transfer_dtype})
+    if (dt < TLT_F64 || dt > TLT_F16) return fail(&c->err, TLT_E_ARG, "unknown dtype");
+  if ((d->value_dtype == TLT_F64) != (d->transfer_dtype == TLT_F64))
+    return fail(&c->err, TLT_E_ARG, "transfer is F64 exactly when the transport is F64");
+  if (!d->transfer || !d->area || !d->perm || !d->r_nodes || !d->basis)
+    return fail(&c->err, TLT_E_ARG, "NULL geometry array");
+  if (!d->col && !d->position) return fail(&c->err, TLT_E_ARG, "need col/val or position");
+  if (d->col && !d->val) return fail(&c->err, TLT_E_ARG, "col given without val");
+  {
+    std::vector<char> seen(N, 0);
+    for (int i = 0; i < N; ++i) {
+      const int p = d->perm[i];
+      if (p < 0 || p >= N || seen[p]) return fail(&c->err, TLT_E_FORMAT, "perm is not a permutation");
+      seen[p] = 1;
+    }
+  }
+  for (int i = 0; i < N; ++i)
+    if (!(d->area[i] > 0.0) || !std::isfinite(d->area[i]))
+      return fail(&c->err, TLT_E_ARG, "areas must be positive and finite");
+
+  // validate a given transport before touching the device
+  const int64_t n_rowsW = (int64_t)N * d->K;
+  if (d->col) {
+    for (int64_t r = 0; r < n_rowsW; ++r) {
+      const int32_t *cr = d->col + r * d->n_keep;
+      for (int64_t e = 0; e < d->n_keep; ++e) {
+        if (cr[e] < 0 || cr[e] >= n_cols)
+          return fail(&c->err, TLT_E_FORMAT, "column index out of range in row " + std::to_string(r));
+        if (e > 0 && cr[e] <= cr[e - 1])
+          return fail(&c->err, TLT_E_FORMAT, "columns not ascending in row " + std::to_string(r));
+      }
+    }
+  }
+
+  HIPC(c, hipDeviceSynchronize());
+  free_all(c);
+  c->N = N;
+  c->n_pad = n_pad;
+  c->n_rows = n_cols;
+  c->n_sh = d->n_sh;
+  c->n_shp = round_up(d->n_sh, 4);
+  c->K = d->K;
+  c->nr = d->n_r;
+  c->wavelet = d->wavelet;
+  c->vdt = d->value_dtype;
+  c->tdt = d->transfer_dtype;
+  c->n_keep = d->n_keep;
+  c->fp64 = d->value_dtype == TLT_F64;
+  c->esz = c->fp64 ? 8 : 4;
+  c->has_range = d->mat_range != nullptr;
+  if (c->has_range) std::memcpy(c->mat_range, d->mat_range, sizeof(c->mat_range));
+
+  tlt_status s;
+  const size_t vsz = dtype_size(c->vdt);
+  const size_t nnz = (size_t)n_rowsW * (size_t)d->n_keep;
+  if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, &c->val, vsz * nnz, "transport values")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, &c->T, dtype_size(c->tdt) * (size_t)N * c->n_sh, "transfer")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, &c->area, c->esz * N, "areas")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, (void **)&c->perm, sizeof(int32_t) * N, "perm")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, (void **)&c->rn, sizeof(double) * c->nr, "r nodes")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, (void **)&c->basis, sizeof(double) * c->nr * c->K, "basis")) != TLT_OK) goto fail_all;
+  {
+    hipError_t he = hipSuccess;
+#define HTRY(x) if ((he = (x)) != hipSuccess) { s = hip_fail(c, he, #x); goto fail_all; }
+    HTRY(hipMemcpy(c->perm, d->perm, sizeof(int32_t) * N, hipMemcpyHostToDevice));
+    HTRY(hipMemcpy(c->rn, d->r_nodes, sizeof(double) * c->nr, hipMemcpyHostToDevice));
+    HTRY(hipMemcpy(c->basis, d->basis, sizeof(double) * c->nr * c->K, hipMemcpyHostToDevice));
+    if (c->fp64) {
+      HTRY(hipMemcpy(c->area, d->area, sizeof(double) * N, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> a(N);
+      for (int i = 0; i < N; ++i) a[i] = (float)d->area[i];
+      HTRY(hipMemcpy(c->area, a.data(), sizeof(float) * N, hipMemcpyHostToDevice));
+    }
+    // staging buffer for float64 -> storage conversion
+    const size_t stage_elems = (size_t)1 << 24;
+    double *stage = nullptr;
+    if ((s = dalloc(c, (void **)&stage, sizeof(double) * stage_elems, "staging")) != TLT_OK) goto fail_all;
+    auto upload_q = [&](const double *src, void *dst, int dt, size_t n) -> hipError_t {
+      for (size_t o = 0; o < n; o += stage_elems) {
+        const size_t m = std::min(stage_elems, n - o);
+        hipError_t e2 = hipMemcpy(stage, src + o, sizeof(double) * m, hipMemcpyHostToDevice);
+        if (e2 != hipSuccess) return e2;
+        e2 = launch_quantize(stage, (char *)dst + o * dtype_size(dt), dt, (int64_t)m, 0);
+        if (e2 != hipSuccess) return e2;
+        e2 = hipStreamSynchronize(0);
+        if (e2 != hipSuccess) return e2;
+      }
+      return hipSuccess;
+    };
+    he = upload_q(d->transfer, c->T, c->tdt, (size_t)N * c->n_sh);
+    if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transfer"); goto fail_all; }
+    if (d->col) {
+      he = hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
+      if (he == hipSuccess) he = hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice);
+      if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transport"); goto fail_all; }
+    } else {
+      // Build rows on the host in blocks of vertices, upload each block.
+      const int nth = host_threads();
+      const int64_t per_row = (int64_t)c->K * d->n_keep;
+      int64_t vb = std::max<int64_t>(1, (int64_t)(96 << 20) / std::max<int64_t>(1, per_row * 12));
+      vb = std::min<int64_t>(vb, N);
+      std::vector<int32_t> hc;
+      std::vector<double> hv;
+      try {
+        hc.resize((size_t)(vb * per_row));
+        hv.resize((size_t)(vb * per_row));
+      } catch (...) {
+        dfree(stage);
+        s = fail(&c->err, TLT_E_OOM, "host staging for the transport build");
+        goto fail_all;
+      }
+      for (int64_t o0 = 0; o0 < N; o0 += vb) {
+        const int64_t nv = std::min<int64_t>(vb, N - o0);
+        host_build_rows((int)nv, n_cols, c->K, c->nr, c->wavelet, d->n_keep, d->position + 3 * o0,
+                        d->r_nodes, d->basis, hc.data(), hv.data(), nth, N, d->position);
+        const size_t off = (size_t)(o0 * per_row);
+        const size_t m = (size_t)(nv * per_row);
+        he = hipMemcpy(c->col + off, hc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice);
+        if (he == hipSuccess) he = upload_q(hv.data(), (char *)c->val + off * vsz, c->vdt, m);
+        if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading built transport"); goto fail_all; }
+      }
+    }
+    dfree(stage);
+#undef HTRY
+  }
+  if ((s = ensure_P(c, 0)) != TLT_OK) goto fail_all;
+  c->loaded = true;
+  c->mat_dirty = c->light_dirty = true;
+  return TLT_OK;
+fail_all:
+  free_all(c);
+  return s;
+}
+
+tlt_status set_material(tlt_ctx *c, int n_mat, const double *theta_dev, void *stream) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_material before load_transport");
+  if (n_mat < 1 || !theta_dev) return fail(&c->err, TLT_E_ARG, "need n_mat >= 1 and a pointer");
+  std::vector<double> h((size_t)n_mat * 9);
+  hipStream_t st = (hipStream_t)stream;
+  HIPC(c, hipMemcpyAsync(h.data(), theta_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+  HIPC(c, hipStreamSynchronize(st));
+  bool out_of_range = false;
+  for (int i = 0; i < n_mat * 3; ++i) {
+    const double sa = h[3 * i], ss = h[3 * i + 1], eta = h[3 * i + 2];
+    if (!std::isfinite(sa) || !std::isfinite(ss) || !std::isfinite(eta) || !(sa > 0) || !(ss > 0) ||
+        !(eta >= 1.0))
+      return fail(&c->err, TLT_E_ARG,
+                  "material " + std::to_string(i / 3) + " channel " + std::to_string(i % 3) +
+                      ": need sigma_a > 0, sigma_s' > 0, eta >= 1, all finite");
+    if (c->has_range) {
+      const double v[3] = {sa, ss, eta};
+      for (int p = 0; p < 3; ++p)
+        if (v[p] < c->mat_range[2 * p] || v[p] > c->mat_range[2 * p + 1]) out_of_range = true;
+    }
+  }
+  c->theta = theta_dev;
+  c->n_mat = n_mat;
+  c->mat_dirty = true;
+  if (out_of_range) {
+    c->err = "material outside the range of the PCA table";
+    return TLT_W_MATERIAL_OUT_OF_RANGE;
+  }
+  return TLT_OK;
+}
+
+tlt_status set_lighting(tlt_ctx *c, int n_light, const void *sh_dev) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_lighting before load_transport");
+  if (n_light < 1 || !sh_dev) return fail(&c->err, TLT_E_ARG, "need n_light >= 1 and a pointer");
+  c->sh = sh_dev;
+  c->n_light = n_light;
+  c->light_dirty = true;
+  c->v_valid = false;
+  return TLT_OK;
+}
+
+tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "render before load_transport");
+  if (!c->sh || !c->theta) return fail(&c->err, TLT_E_STATE, "render before set_lighting/set_material");
+  if (!B) return fail(&c->err, TLT_E_ARG, "B is NULL");
+  if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
+    return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
+  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL)) return fail(&c->err, TLT_E_ARG, "unknown flags");
+  hipStream_t st = (hipStream_t)stream;
+  tlt_status s;
+  if ((s = ensure_columns(c)) != TLT_OK) return s;
+  const bool save = flags & TLT_SAVE_FOR_BACKWARD;
+  const bool full = flags & TLT_FORCE_FULL;
+  if (save && (s = ensure_V(c)) != TLT_OK) return s;
+  Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
+  if (c->mat_dirty || full)
+    HIPC(c, launch_gk(c->theta, c->rn, c->basis, c->nr, c->K, c->g64, c->dg64, c->gcol, c->fp64,
+                      c->Cs, cols, st));
+  const bool relight = c->light_dirty || full || !(c->v_valid);
+  if (!relight && c->V) {
+    // material-only edit: reuse the saved per-term transport v_k
+    HIPC(c, launch_combine(c->V, c->Cs, c->gcol, c->K, c->N, c->C, c->perm, B, c->fp64, st));
+  } else {
+    HIPC(c, launch_lmat(c->sh, c->fp64, c->n_sh, c->n_shp, c->Cs, cols, c->Lm, st));
+    HIPC(c, launch_tl_haar(c->T, c->tdt, c->N, c->n_sh, c->n_shp, c->Lm, c->area, c->fp64,
+                           c->wavelet == TLT_WAVELET_HAAR, c->n_rows, c->Cs, c->ehat, c->partial, st));
+    HIPC(c, launch_transport(c->col, c->val, c->vdt, c->n_keep, c->K, c->N, c->ehat, c->Cs, c->C,
+                             c->cpl, c->gcol, c->perm, B, save ? c->V : nullptr, c->Cs, c->fp64, st));
+    c->v_valid = save;
+  }
+  c->mat_dirty = false;
+  c->light_dirty = false;
+  return TLT_OK;
+}
+
+tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta, void *stream) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded || !c->v_valid || !c->have_P || c->mat_dirty || c->light_dirty)
+    return fail(&c->err, TLT_E_STATE,
+                "render_backward needs a render with TLT_SAVE_FOR_BACKWARD of the current inputs");
+  if (!dB || !dSH || !dTheta) return fail(&c->err, TLT_E_ARG, "NULL gradient pointer");
+  hipStream_t st = (hipStream_t)stream;
+  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->fp64);
+  if (c->adj_bytes < need) {
+    dfree(c->adj);
+    c->adj_bytes = 0;
+    tlt_status s = dalloc(c, &c->adj, need, "adjoint partials");
+    if (s != TLT_OK) return s;
+    c->adj_bytes = need;
+  }
+  Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
+  HIPC(c, launch_adjoint(dB, c->V, c->Cs, c->P, c->Psh, c->gcol, c->dg64, c->perm, c->N, c->K,
+                         c->n_sh, cols, c->fp64, c->adj, c->adj_bytes, dSH, dTheta, st));
+  return TLT_OK;
+}
+
+tlt_status tlt_read_rows(tlt_ctx *c, int64_t n_rows, const int64_t *rows, int32_t *col_out,
+                         double *val_out) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "no transport loaded");
+  if (n_rows < 0 || (n_rows > 0 && (!rows || !col_out || !val_out)))
+    return fail(&c->err, TLT_E_ARG, "bad arguments");
+  const int64_t total = (int64_t)c->N * c->K;
+  const size_t vsz = dtype_size(c->vdt);
+  std::vector<unsigned char> raw(vsz * c->n_keep);
+  HIPC(c, hipDeviceSynchronize());
+  for (int64_t i = 0; i < n_rows; ++i) {
+    if (rows[i] < 0 || rows[i] >= total) return fail(&c->err, TLT_E_ARG, "row out of range");
+    const size_t off = (size_t)rows[i] * c->n_keep;
+    HIPC(c, hipMemcpy(col_out + i * c->n_keep, c->col + off, sizeof(int32_t) * c->n_keep,
+                      hipMemcpyDeviceToHost));
+    HIPC(c, hipMemcpy(raw.data(), (char *)c->val + off * vsz, vsz * c->n_keep, hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < c->n_keep; ++e) val_out[i * c->n_keep + e] = widen(raw.data(), c->vdt, e);
+  }
+  return TLT_OK;
+}
+
+tlt_status tlt_read_state(tlt_ctx *c, int which, void *out, size_t *bytes, int *c_stride) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->ehat) return fail(&c->err, TLT_E_STATE, "nothing rendered yet");
+  const void *src = nullptr;
+  size_t n = 0;
+  switch (which) {
+    case 0: src = c->ehat; n = c->esz * (size_t)c->n_rows * c->Cs; break;
+    case 1: src = c->g64; n = sizeof(double) * c->n_mat * 3 * c->K; break;
+    case 2: src = c->dg64; n = sizeof(double) * c->n_mat * 9 * c->K; break;
+    default: return fail(&c->err, TLT_E_ARG, "unknown state id");
+  }
+  if (c_stride) *c_stride = c->Cs;
+  if (bytes) *bytes = n;
+  if (!out) return TLT_OK;
+  HIPC(c, hipDeviceSynchronize());
+  HIPC(c, hipMemcpy(out, src, n, hipMemcpyDeviceToHost));
+  return TLT_OK;
+}
+
+}  // extern "C"

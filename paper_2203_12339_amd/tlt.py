@@ -1,0 +1,340 @@
+"""ctypes binding of libtlt.so (argument marshalling only).
+
+Every computation runs inside the library: host precompute in C++, the
+per-frame path in HIP kernels on the GPU.  PyTorch supplies device memory
+and the current HIP stream.  If the library is missing this module raises
+at import time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtlt.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+WAVELET_NONE, WAVELET_HAAR = 0, 1
+SAVE_FOR_BACKWARD, FORCE_FULL = 1, 2
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
+
+OK = 0
+W_MATERIAL_OUT_OF_RANGE = 1
+STATUS = {0: "TLT_OK", 1: "TLT_W_MATERIAL_OUT_OF_RANGE", -1: "TLT_E_ARG", -2: "TLT_E_STATE",
+          -3: "TLT_E_OOM", -4: "TLT_E_HIP", -5: "TLT_E_FORMAT"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_p = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class SceneDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int32), ("n_faces", ctypes.c_int32),
+        ("vertices", _f64p), ("faces", _i32p),
+        ("n_sh", ctypes.c_int32), ("K", ctypes.c_int32), ("n_r", ctypes.c_int32),
+        ("r_max", ctypes.c_double),
+        ("mat_lo", ctypes.c_double * 3), ("mat_hi", ctypes.c_double * 3),
+        ("mat_n", ctypes.c_int32 * 3),
+        ("perm", _i32p), ("position", _f64p), ("area", _f64p), ("normal", _f64p),
+        ("transfer", _f64p), ("r_nodes", _f64p), ("basis", _f64p),
+        ("singular_values", _f64p),
+    ]
+
+
+class TransportDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", ctypes.c_int32), ("n_pad", ctypes.c_int32), ("n_sh", ctypes.c_int32),
+        ("K", ctypes.c_int32), ("n_r", ctypes.c_int32), ("wavelet", ctypes.c_int32),
+        ("value_dtype", ctypes.c_int32), ("transfer_dtype", ctypes.c_int32),
+        ("n_keep", ctypes.c_int64),
+        ("col", _i32p), ("val", _p), ("position", _f64p), ("transfer", _f64p),
+        ("area", _f64p), ("perm", _i32p), ("r_nodes", _f64p), ("basis", _f64p),
+        ("mat_range", _f64p),
+    ]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_prepare_scene = _sig("tlt_prepare_scene", ctypes.c_int, ctypes.POINTER(SceneDesc))
+_create = _sig("tlt_create", ctypes.c_int, ctypes.POINTER(_p), ctypes.c_int)
+_destroy = _sig("tlt_destroy", None, _p)
+_last_error = _sig("tlt_last_error", ctypes.c_char_p, _p)
+_load_transport = _sig("load_transport", ctypes.c_int, _p, ctypes.POINTER(TransportDesc))
+_set_material = _sig("set_material", ctypes.c_int, _p, ctypes.c_int, _p, _p)
+_set_lighting = _sig("set_lighting", ctypes.c_int, _p, ctypes.c_int, _p)
+_render = _sig("render", ctypes.c_int, _p, _p, _p, ctypes.c_int)
+_render_backward = _sig("render_backward", ctypes.c_int, _p, _p, _p, _p, _p)
+_read_rows = _sig("tlt_read_rows", ctypes.c_int, _p, ctypes.c_int64,
+                  ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
+_read_state = _sig("tlt_read_state", ctypes.c_int, _p, ctypes.c_int, _p,
+                   ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int))
+_set_tile = _sig("tlt_set_tile", ctypes.c_int, _p, ctypes.c_int)
+_get_tile = _sig("tlt_get_tile", ctypes.c_int, _p)
+_version = _sig("tlt_version", ctypes.c_char_p)
+_build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _f64p, _f64p, _f64p,
+                   ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
+
+EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
+            "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
+            "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version"]
+
+
+class TltError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, ctx=None, allow=(OK,)):
+    if status in allow:
+        return status
+    msg = _last_error(ctx).decode(errors="replace")
+    raise TltError(status, msg)
+
+
+def version() -> str:
+    return _version().decode()
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+# ---------------------------------------------------------------------------
+# Host precompute
+# ---------------------------------------------------------------------------
+
+def prepare_scene(vertices, faces, n_sh, K, n_r, r_max, grid):
+    """Geometry + PCA precompute in the library (host C++, float64).
+
+    grid: dict(sigma_a=(lo, hi, n), sigma_s=(lo, hi, n), eta=(lo, hi, n)).
+    Returns a dict of numpy arrays (Morton order where per vertex).
+    """
+    V = np.ascontiguousarray(vertices, dtype=np.float64)
+    F = np.ascontiguousarray(faces, dtype=np.int32)
+    N = V.shape[0]
+    n_mat = int(np.prod([grid[k][2] for k in ("sigma_a", "sigma_s", "eta")]))
+    out = dict(perm=np.empty(N, np.int32), position=np.empty((N, 3)), area=np.empty(N),
+               normal=np.empty((N, 3)), transfer=np.empty((N, n_sh)), r_nodes=np.empty(n_r),
+               basis=np.empty((K, n_r)), singular_values=np.empty(min(n_mat, n_r)))
+    d = SceneDesc()
+    d.n_vertices, d.n_faces = N, F.shape[0]
+    d.vertices, d.faces = _ptr(V, ctypes.c_double), _ptr(F, ctypes.c_int32)
+    d.n_sh, d.K, d.n_r, d.r_max = n_sh, K, n_r, float(r_max)
+    keys = ("sigma_a", "sigma_s", "eta")
+    d.mat_lo = (ctypes.c_double * 3)(*[grid[k][0] for k in keys])
+    d.mat_hi = (ctypes.c_double * 3)(*[grid[k][1] for k in keys])
+    d.mat_n = (ctypes.c_int32 * 3)(*[grid[k][2] for k in keys])
+    d.perm = _ptr(out["perm"], ctypes.c_int32)
+    for k in ("position", "area", "normal", "transfer", "r_nodes", "basis", "singular_values"):
+        setattr(d, k, _ptr(out[k], ctypes.c_double))
+    _check(_prepare_scene(ctypes.byref(d)), None)
+    out["mat_range"] = np.array([[grid[k][0], grid[k][1]] for k in keys], dtype=np.float64)
+    return out
+
+
+def build_rows(scene, n_keep, wavelet, morton_rows):
+    """Host float64 transport rows (as load_transport builds them) for the
+    given Morton positions -> (col [R, K, n_keep] int32, val [R, K, n_keep])."""
+    pos = np.ascontiguousarray(scene["position"], dtype=np.float64)
+    rn = np.ascontiguousarray(scene["r_nodes"], dtype=np.float64)
+    b = np.ascontiguousarray(scene["basis"], dtype=np.float64)
+    N = pos.shape[0]
+    K = b.shape[0]
+    n_cols = (1 << (N - 1).bit_length()) if wavelet == "haar" else N
+    rows = np.ascontiguousarray(morton_rows, dtype=np.int64)
+    col = np.empty((len(rows), K, n_keep), np.int32)
+    val = np.empty((len(rows), K, n_keep), np.float64)
+    _check(_build_rows(N, n_cols, K, rn.shape[0], WAVELET_HAAR if wavelet == "haar" else WAVELET_NONE,
+                       n_keep, _ptr(pos, ctypes.c_double), _ptr(rn, ctypes.c_double),
+                       _ptr(b, ctypes.c_double), len(rows), _ptr(rows, ctypes.c_int64),
+                       _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double)), None)
+    return col, val
+
+
+# ---------------------------------------------------------------------------
+# Context wrapper
+# ---------------------------------------------------------------------------
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Renderer:
+    """One library context holding one loaded transport.
+
+    The C-ABI calls of the same names: load_transport, set_material,
+    set_lighting, render, render_backward.
+    """
+
+    def __init__(self, device: int = 0):
+        import torch
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(_create(ctypes.byref(h), device), None)
+        self._h = h
+        self.loaded = False
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return _last_error(self._h).decode(errors="replace")
+
+    # -- transport --------------------------------------------------------
+    def load_transport(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None):
+        N = scene["perm"].shape[0]
+        n_pad = 1 << (N - 1).bit_length()
+        vdt = DTYPES[storage]
+        self.N, self.n_pad = N, n_pad
+        self.n_sh = scene["transfer"].shape[1]
+        self.K = scene["basis"].shape[0]
+        self.fp64 = vdt == F64
+        self.storage = storage
+        self.wavelet = WAVELET_HAAR if wavelet == "haar" else WAVELET_NONE
+        self.n_keep = int(n_keep)
+        self.perm = np.ascontiguousarray(scene["perm"], dtype=np.int32)
+        arrs = {k: np.ascontiguousarray(scene[k], dtype=np.float64)
+                for k in ("position", "transfer", "area", "r_nodes", "basis")}
+        mr = np.ascontiguousarray(scene.get("mat_range"), dtype=np.float64) \
+            if scene.get("mat_range") is not None else None
+        d = TransportDesc()
+        d.n_vertices, d.n_pad, d.n_sh, d.K = N, n_pad, self.n_sh, self.K
+        d.n_r = arrs["r_nodes"].shape[0]
+        d.wavelet = self.wavelet
+        d.value_dtype = vdt
+        d.transfer_dtype = vdt
+        d.n_keep = self.n_keep
+        if col is not None:
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            d.col = _ptr(col, ctypes.c_int32)
+            d.val = val.ctypes.data_as(ctypes.c_void_p)
+        d.position = _ptr(arrs["position"], ctypes.c_double)
+        d.transfer = _ptr(arrs["transfer"], ctypes.c_double)
+        d.area = _ptr(arrs["area"], ctypes.c_double)
+        d.perm = _ptr(self.perm, ctypes.c_int32)
+        d.r_nodes = _ptr(arrs["r_nodes"], ctypes.c_double)
+        d.basis = _ptr(arrs["basis"], ctypes.c_double)
+        if mr is not None:
+            d.mat_range = _ptr(mr, ctypes.c_double)
+        _check(_load_transport(self._h, ctypes.byref(d)), self._h)
+        self.loaded = True
+        return self
+
+    # -- inputs -----------------------------------------------------------
+    def set_material(self, theta):
+        """theta: CUDA float64 tensor [n_mat, 3, 3]. Returns the status."""
+        import torch
+        assert theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous()
+        self._theta = theta
+        self.n_mat = theta.shape[0]
+        return _check(_set_material(self._h, theta.shape[0], ctypes.c_void_p(theta.data_ptr()),
+                                    _stream()), self._h, allow=(OK, W_MATERIAL_OUT_OF_RANGE))
+
+    def set_lighting(self, sh):
+        """sh: CUDA tensor [n_light, n_sh, 3] (float64 for F64 storage)."""
+        import torch
+        want = torch.float64 if self.fp64 else torch.float32
+        assert sh.is_cuda and sh.dtype == want and sh.is_contiguous(), (sh.dtype, want)
+        assert sh.shape[1] == self.n_sh and sh.shape[2] == 3
+        self._sh = sh
+        self.n_light = sh.shape[0]
+        return _check(_set_lighting(self._h, sh.shape[0], ctypes.c_void_p(sh.data_ptr())), self._h)
+
+    @property
+    def n_out(self):
+        return max(self.n_light, self.n_mat)
+
+    def out_dtype(self):
+        import torch
+        return torch.float64 if self.fp64 else torch.float32
+
+    def render(self, out=None, save=False, force=False):
+        import torch
+        if out is None:
+            out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
+                              device=self.torch_device)
+        flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0)
+        _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags), self._h)
+        return out
+
+    def render_raw(self, out_ptr: int, flags: int):
+        """Render into a raw device pointer (for graph capture and timing)."""
+        return _check(_render(self._h, ctypes.c_void_p(out_ptr), _stream(), flags), self._h)
+
+    def render_backward(self, dB, dSH=None, dTheta=None):
+        import torch
+        dB = dB.contiguous()
+        if dSH is None:
+            dSH = torch.empty((self.n_light, self.n_sh, 3), dtype=self.out_dtype(),
+                              device=self.torch_device)
+        if dTheta is None:
+            dTheta = torch.empty((self.n_mat, 3, 3), dtype=torch.float64,
+                                 device=self.torch_device)
+        _check(_render_backward(self._h, ctypes.c_void_p(dB.data_ptr()),
+                                ctypes.c_void_p(dSH.data_ptr()),
+                                ctypes.c_void_p(dTheta.data_ptr()), _stream()), self._h)
+        return dSH, dTheta
+
+    # -- diagnostics ------------------------------------------------------
+    def read_rows(self, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        col = np.empty((len(rows), self.n_keep), np.int32)
+        val = np.empty((len(rows), self.n_keep), np.float64)
+        _check(_read_rows(self._h, len(rows), _ptr(rows, ctypes.c_int64),
+                          _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double)), self._h)
+        return col, val
+
+    def read_state(self, which):
+        nbytes = ctypes.c_size_t()
+        stride = ctypes.c_int()
+        _check(_read_state(self._h, which, None, ctypes.byref(nbytes), ctypes.byref(stride)),
+               self._h)
+        buf = np.empty(nbytes.value, np.uint8)
+        _check(_read_state(self._h, which, buf.ctypes.data_as(ctypes.c_void_p),
+                           ctypes.byref(nbytes), ctypes.byref(stride)), self._h)
+        return buf, stride.value
+
+    def ehat(self):
+        buf, cs = self.read_state(0)
+        dt = np.float64 if self.fp64 else np.float32
+        rows = self.n_pad if self.wavelet == WAVELET_HAAR else self.N
+        return buf.view(dt).reshape(rows, cs)
+
+    def g(self):
+        buf, _ = self.read_state(1)
+        return buf.view(np.float64).reshape(self.n_mat, 3, self.K)
+
+    def dg(self):
+        buf, _ = self.read_state(2)
+        return buf.view(np.float64).reshape(self.n_mat, 3, self.K, 3)
+
+    def set_tile(self, cpl: int):
+        _check(_set_tile(self._h, int(cpl)), self._h)
+
+    def tile(self) -> int:
+        return int(_get_tile(self._h))

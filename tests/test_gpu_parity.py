@@ -1,0 +1,222 @@
+"""GPU parity of the full hot path against the FP64 oracle (through the C ABI).
+
+Tolerances (normwise per output set and channel, ||B - B_ref||_inf /
+||B_ref||_inf): FP64 storage 1e-10, FP32 storage 1e-5, BF16/FP16 storage
+5e-3, each against the oracle's unquantised float64 operator on the same
+kept sets.  Kept sets are integer decisions taken in float64 on both sides
+and compared exactly.
+"""
+import numpy as np
+import pytest
+
+import synth
+from _helpers import dev_tensor, elementwise, light_dtype, normwise, oracle_scene, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2203_12339_amd import tlt  # noqa: E402
+from paper_2203_12339_amd.workloads import renderer_for, scene_for  # noqa: E402
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 5e-3, "f16": 5e-3}
+
+
+def _render(w, L=None, th=None, save=False, renderer=None):
+    r = renderer or renderer_for(w)
+    L = synth.make_lighting(w) if L is None else L
+    th = synth.make_materials(w) if th is None else th
+    r.set_lighting(dev_tensor(L, light_dtype(w)))
+    r.set_material(dev_tensor(th, "f64"))
+    B = r.render(save=save, force=True)
+    torch.cuda.synchronize()
+    return r, L, th, B.cpu().numpy()
+
+
+CASES = [
+    ("c1", {}),
+    ("c1-haar-untruncated", dict(wavelet="haar")),
+    ("c2", {}),
+    ("c2-small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
+    ("c2-tiny", dict(subdiv=0, keep=0.5)),
+    ("c2-batched", dict(subdiv=4, n_light=5, n_cfg=5)),
+    ("c3", {}),
+    ("c3-f32", dict(storage="f32", wavelet="haar", keep=None)),
+    ("c4-shrunk", dict(subdiv=4, n_light=64, n_cfg=64)),
+    ("c5-shrunk", dict(subdiv=4, n_light=16, n_cfg=1, sample_rows=0)),
+]
+
+
+def _workload(name, kw):
+    return synth.get(name.split("-")[0]).with_(**kw)
+
+
+@pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
+def test_render_matches_oracle(name, kw):
+    w = _workload(name, kw)
+    say(f"[parity] {name}: N={w.n_vertices} K={w.K} n_keep={w.n_keep} storage={w.storage} "
+        f"wavelet={w.wavelet} n_out={w.n_out}")
+    r, L, th, B = _render(w)
+    ref = oracle_scene(w).render(L, th)
+    e = normwise(B, ref)
+    say(f"[parity] {name}: normwise {e:.3e} elementwise {elementwise(B, ref):.3e}")
+    assert e <= TOL[w.storage], e
+    r.close()
+
+
+def test_untruncated_wavelet_equals_plain_fp64():
+    """Eq. (8): with nothing truncated the Haar form equals the plain form."""
+    w = synth.get("c1")
+    say("[parity] untruncated haar vs plain, FP64")
+    r1, L, th, B1 = _render(w)
+    r2, _, _, B2 = _render(w.with_(wavelet="haar"), L, th)
+    assert normwise(B2, B1) <= 1e-12
+    r1.close()
+    r2.close()
+
+
+def test_stored_rows_match_host_build_and_oracle():
+    w = synth.get("c2").with_(subdiv=4)
+    say("[rows] c2 subdiv 4")
+    r = renderer_for(w)
+    o = oracle_scene(w)
+    m_rows = np.arange(0, w.n_vertices, 61)
+    rows = (m_rows[:, None] * w.K + np.arange(w.K)[None, :]).reshape(-1)
+    col, val = r.read_rows(rows)
+    oc, ov = o.kept_lists(m_rows)                     # [K, P, n]
+    oc = oc.transpose(1, 0, 2).reshape(len(rows), -1)
+    ov = ov.transpose(1, 0, 2).reshape(len(rows), -1)
+    assert np.array_equal(col, oc)
+    np.testing.assert_allclose(val, ov.astype(np.float32), rtol=1e-6, atol=1e-6 * np.abs(ov).max())
+    r.close()
+
+
+def test_intermediates_ehat_and_weights():
+    w = synth.get("c2").with_(subdiv=4, n_light=2, n_cfg=2)
+    say("[intermediates] Ehat, g, dg")
+    r, L, th, _ = _render(w)
+    o = oracle_scene(w)
+    eh = r.ehat()[:, :w.n_out * 3].reshape(-1, w.n_out, 3).transpose(1, 0, 2)
+    ref = o.ehat(L)
+    assert normwise(eh, ref) <= 2e-6
+    from oracle import pca
+    g = pca.weights(th, o.rn, o.b)
+    np.testing.assert_allclose(r.g(), g, rtol=1e-11, atol=1e-13 * np.abs(g).max())
+    dg = pca.weight_grads(th, o.rn, o.b)
+    np.testing.assert_allclose(r.dg(), dg, rtol=1e-10, atol=1e-12 * np.abs(dg).max())
+    r.close()
+
+
+def test_linearity_and_material_only_update():
+    w = synth.get("c2").with_(subdiv=4, n_light=3, n_cfg=1)
+    say("[invariants] linearity, material-only update")
+    L = synth.make_lighting(w)
+    L[2] = 2 * L[0] - 0.5 * L[1]
+    r, _, th, B = _render(w, L=L, save=True)
+    np.testing.assert_allclose(B[2], 2 * B[0] - 0.5 * B[1], atol=5e-6 * np.abs(B).max())
+    # material edit: the saved v_k are reused (Steps 3-4 only)
+    th2 = synth.make_materials(w, seed=999)
+    r.set_material(dev_tensor(th2, "f64"))
+    Bm = r.render().cpu().numpy()
+    r.set_material(dev_tensor(th2, "f64"))
+    Bf = r.render(force=True).cpu().numpy()
+    assert normwise(Bm, Bf) <= 2e-6
+    ref = oracle_scene(w).render(L, th2)
+    assert normwise(Bm, ref) <= 1e-5
+    r.close()
+
+
+def test_autograd_c3_fp64_gradients():
+    """Gradient of the L2 loss vs the FP64 oracle adjoint and central FD."""
+    from oracle import adjoint
+    from paper_2203_12339_amd.autograd import render as trender
+    w = synth.get("c3")
+    say("[grad] c3 FP64")
+    o = oracle_scene(w)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    Lt, tht = synth.perturb_target(w, L, th)
+    Bt = o.render(Lt, tht)
+    r = renderer_for(w)
+    sh = dev_tensor(L, "f64").requires_grad_(True)
+    tt = dev_tensor(th, "f64").requires_grad_(True)
+    B = trender(r, sh, tt)
+    loss = 0.5 * ((B - dev_tensor(Bt, "f64")) ** 2).sum()
+    loss.backward()
+    gL_ref, gT_ref = adjoint.grad(o, L, th, o.render(L, th) - Bt)
+    gL = sh.grad.cpu().numpy()
+    gT = tt.grad.cpu().numpy()
+    np.testing.assert_allclose(gL, gL_ref, rtol=1e-9, atol=1e-11 * np.abs(gL_ref).max())
+    np.testing.assert_allclose(gT, gT_ref, rtol=1e-9, atol=1e-11 * np.abs(gT_ref).max())
+    fL, fT = adjoint.fd_grad(o, L, th, Bt)
+    np.testing.assert_allclose(gL, fL, rtol=1e-5, atol=1e-8 * np.abs(fL).max())
+    np.testing.assert_allclose(gT, fT, rtol=1e-5, atol=1e-8 * np.abs(fT).max())
+    say(f"[grad] c3 FP64 ok |gL|={np.abs(gL).max():.3e} |gT|={np.abs(gT).max():.3e}")
+    r.close()
+
+
+@pytest.mark.parametrize("name,kw", [("c3-f32", dict(storage="f32", wavelet="haar")),
+                                     ("c2-batched", dict(subdiv=3, n_light=4, n_cfg=4)),
+                                     ("c5-shrunk", dict(subdiv=3, n_light=6, n_cfg=1))],
+                         ids=["c3-f32", "c2-batched", "c5-shrunk"])
+def test_adjoint_fp32_matches_oracle(name, kw):
+    from oracle import adjoint
+    w = _workload(name, kw)
+    say(f"[grad] {name}")
+    o = oracle_scene(w)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    r, _, _, B = _render(w, L, th, save=True)
+    rng = np.random.default_rng(7)
+    bb = rng.standard_normal(B.shape)
+    dSH, dTh = r.render_backward(dev_tensor(bb, "f32"))
+    gL_ref, gT_ref = adjoint.grad(o, L, th, bb)
+    gL = dSH.cpu().numpy()
+    gT = dTh.cpu().numpy()
+    tol = TOL[w.storage]
+    for g, ref in ((gL, gL_ref), (gT, gT_ref)):
+        err = np.abs(g - ref).max() / np.abs(ref).max()
+        say(f"[grad] {name}: rel err {err:.3e} (tol {tol:.0e})")
+        assert err <= tol, err
+    # dot-product test in the lighting direction, all on the GPU
+    dL = rng.standard_normal(L.shape)
+    _, _, _, BdL = _render(w, dL, th, renderer=r)
+    lhs = float(np.sum(bb * BdL))
+    rhs = float(np.sum(gL * dL))
+    # exact transpose of the stored operator: agreement to float32 rounding
+    assert abs(lhs - rhs) <= 1e-5 * (np.abs(bb).sum() * np.abs(BdL).max()), (lhs, rhs)
+    r.close()
+
+
+def test_error_paths_on_device():
+    w = synth.get("c2").with_(subdiv=2)
+    say("[errors] status codes")
+    r = tlt.Renderer(0)
+    with pytest.raises(tlt.TltError) as ei:
+        r.render_raw(0, 0)
+    assert ei.value.status == -2                      # nothing loaded
+    r.close()
+    r = renderer_for(w)
+    out = torch.empty((1, w.n_vertices, 3), device="cuda:0")
+    with pytest.raises(tlt.TltError) as ei:
+        r.render_raw(out.data_ptr(), 0)
+    assert ei.value.status == -2                      # not set yet
+    bad = synth.make_materials(w)
+    bad[0, 1, 0] = -1.0
+    with pytest.raises(tlt.TltError) as ei:
+        r.set_material(dev_tensor(bad, "f64"))
+    assert ei.value.status == -1
+    far = synth.make_materials(w)
+    far[0, 0, 0] = 0.5                                # sigma_a outside the PCA table
+    assert r.set_material(dev_tensor(far, "f64")) == tlt.W_MATERIAL_OUT_OF_RANGE
+    r.set_lighting(dev_tensor(synth.make_lighting(w), "f32"))
+    r.render()
+    with pytest.raises(tlt.TltError) as ei:
+        r.render_backward(torch.zeros((1, w.n_vertices, 3), device="cuda:0"))
+    assert ei.value.status == -2                      # forward did not save
+    with pytest.raises(tlt.TltError) as ei:
+        r.set_tile(5)
+    assert ei.value.status == -1
+    r.close()

@@ -1,0 +1,97 @@
+"""CPU tests of the native library: exports, host precompute, error paths.
+
+No GPU work is called here: only the host-side entry points
+(tlt_prepare_scene, tlt_build_rows) and symbol lookup.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.transport import Scene
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+tlt = pytest.importorskip("paper_2203_12339_amd.tlt")
+from paper_2203_12339_amd.workloads import scene_for  # noqa: E402
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "tlt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_declared_function():
+    names = _header_functions()
+    assert {"load_transport", "set_material", "set_lighting", "render",
+            "render_backward"} <= set(names)
+    lib = ctypes.CDLL(tlt.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(tlt.EXPORTED)
+    assert "gfx950" in tlt.version()
+
+
+@pytest.mark.parametrize("name", ["c1", "c2", "c5"])
+def test_prepare_scene_matches_oracle(name):
+    w = synth.get(name)
+    if name == "c5":
+        w = w.with_(subdiv=4)
+    sc = scene_for(w)
+    o = Scene(w)
+    p = o.perm
+    assert np.array_equal(sc["perm"], p)                       # index work: exact
+    np.testing.assert_allclose(sc["position"], o.V[p], rtol=0, atol=0)
+    np.testing.assert_allclose(sc["area"], o.area[p], rtol=1e-13)
+    np.testing.assert_allclose(sc["normal"], o.normal[p], atol=1e-14)
+    np.testing.assert_allclose(sc["transfer"], o.T[p], atol=1e-13)
+    np.testing.assert_allclose(sc["r_nodes"], o.rn, rtol=1e-15, atol=0)
+    np.testing.assert_allclose(sc["basis"], o.b, atol=1e-12)
+    np.testing.assert_allclose(sc["singular_values"], o.sv, rtol=1e-10, atol=1e-13 * o.sv[0])
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("c2", {}),
+    ("c1", {}),
+    ("c1", dict(wavelet="haar")),
+    ("c4", dict(subdiv=4)),
+    ("c5", dict(subdiv=3)),
+    ("c2", dict(subdiv=0, keep=0.5)),
+], ids=["c2", "c1-plain", "c1-haar-full", "c4-shrunk", "c5-shrunk", "tiny"])
+def test_build_rows_match_oracle(name, kw):
+    w = synth.get(name).with_(**kw)
+    sc = scene_for(w)
+    o = Scene(w)
+    rows = np.unique(np.concatenate([np.arange(0, w.n_vertices, max(1, w.n_vertices // 40)),
+                                     [w.n_vertices - 1]]))
+    col, val = tlt.build_rows(sc, w.n_keep, w.wavelet, rows)
+    oc, ov = o.kept_lists(rows)
+    oc = oc.transpose(1, 0, 2)
+    ov = ov.transpose(1, 0, 2)
+    assert np.array_equal(col, oc)                             # kept sets: exact
+    np.testing.assert_allclose(val, ov, rtol=1e-11, atol=1e-13 * np.abs(ov).max())
+
+
+def test_host_error_paths():
+    V, F = synth.icosphere(1)
+    grid = synth.MATERIAL_GRID
+    with pytest.raises(tlt.TltError) as ei:
+        tlt.prepare_scene(V, F, 17, 4, 256, 2.0, grid)         # not a square count
+    assert ei.value.status == -1
+    with pytest.raises(tlt.TltError):
+        tlt.prepare_scene(V, F, 16, 0, 256, 2.0, grid)         # K = 0
+    Fb = F.copy()
+    Fb[0, 0] = 10 ** 6
+    with pytest.raises(tlt.TltError):
+        tlt.prepare_scene(V, Fb, 16, 4, 256, 2.0, grid)        # face out of range
+    sc = tlt.prepare_scene(V, F, 16, 4, 256, 2.0, grid)
+    with pytest.raises(tlt.TltError):
+        tlt.build_rows(sc, 1000, "haar", [0])                  # n_keep > n_pad
+    with pytest.raises(tlt.TltError):
+        tlt.build_rows(sc, 4, "haar", [42])                    # row out of range
+    assert "row out of range" in tlt._last_error(None).decode()
