@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of the per-frame translucent transport on one MI355X.
+
+A step is one full pass of the hot path over one batch of synthetic input:
+material weights g_k (FP64), irradiance E = T L (MFMA) with its Haar
+transform, and the wavelet-sparse transport with K-term fusion written in
+original vertex order -- every stage recomputed (TLT_FORCE_FULL).  With
+--backward the step also runs the adjoint.  Inputs are resident in HBM
+before timing starts.  Prints one JSON line on stdout; progress goes to
+stderr.
+
+  python bench.py [--config c2|c4|c5] [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_2203_12339_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload, C):
+    """HBM bytes per transport launch from committed rocprofv3 counters, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"transport_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_hash") != kernel_hash() or d.get("columns") != C:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, L, th, budget_s=12.0):
+    """The FP64 oracle (O-B) on a bounded sample of output rows, 1 thread."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    from oracle.transport import Scene
+    import contextlib
+    sc = Scene(w)
+    rng = np.random.default_rng(12345)
+    limit = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
+    with limit:
+        probe = rng.choice(w.n_vertices, size=min(16, w.n_vertices), replace=False)
+        t0 = time.perf_counter()
+        sc.render_vertices(L, th, probe, block=16)
+        per_row = (time.perf_counter() - t0) / len(probe)
+        n = int(min(w.n_vertices, max(16, budget_s / max(per_row, 1e-6))))
+        rows = np.sort(rng.choice(w.n_vertices, size=n, replace=False))
+        t0 = time.perf_counter()
+        ref = sc.render_vertices(L, th, rows, block=32)
+        dt = time.perf_counter() - t0
+    return rows, ref, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--backward", action="store_true",
+                    help="include the adjoint in every step")
+    ap.add_argument("--tile", type=int, default=0, help="columns per lane (0 = tuned default)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the transport "
+              "shards by Morton row blocks without communication in the forward pass, but "
+              "this build measures the single-GPU kernel.", file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py is single-process; WORLD_SIZE > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2203_12339_amd import tlt
+    from paper_2203_12339_amd.workloads import renderer_for
+
+    w = synth.get(args.config)
+    dev = torch.device("cuda", 0)
+    log(f"[bench] {w.name}: {w.description}; N={w.n_vertices} K={w.K} n_keep={w.n_keep} "
+        f"storage={w.storage} n_light={w.n_light} n_mat={w.n_cfg}")
+    t0 = time.perf_counter()
+    r = renderer_for(w, device=0)
+    if args.tile:
+        r.set_tile(args.tile)
+    log(f"[bench] precompute + load {time.perf_counter() - t0:.1f}s")
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ldt = torch.float64 if w.storage == "f64" else torch.float32
+    sh = torch.tensor(L, dtype=ldt, device=dev)
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    r.set_lighting(sh)
+    r.set_material(tt)
+    B = torch.empty((w.n_out, w.n_vertices, 3), dtype=ldt, device=dev)
+    dB = torch.randn_like(B) if args.backward else None
+    flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0)
+    dSH = torch.empty((w.n_light, w.n_sh, 3), dtype=ldt, device=dev)
+    dTh = torch.empty((w.n_cfg, 3, 3), dtype=torch.float64, device=dev)
+
+    def step():
+        r.render_raw(B.data_ptr(), flags)
+        if args.backward:
+            r.render_backward(dB, dSH, dTh)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    r.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_tr, n_tr = r.profile_read("transport")
+    stage_ms = {s: r.profile_read(s) for s in ("weights", "irradiance", "transport", "adjoint")}
+    r.profile(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    shaded = w.n_vertices * w.n_out
+    value = shaded * args.steps / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f}s -> {ms_per_step:.4f} ms/step; "
+        + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in stage_ms.items()))
+
+    # roofline of the dominant kernel (the transport)
+    C = 3 * w.n_out
+    vsz = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[w.storage]
+    esz = 8 if w.storage == "f64" else 4
+    nnz = w.n_vertices * w.K * w.n_keep
+    n_rows = w.n_pad if w.wavelet == "haar" else w.n_vertices
+    alg_bytes = nnz * (4 + vsz) + n_rows * C * esz + w.n_vertices * C * esz
+    avg_s = ms_tr / max(n_tr, 1) * 1e-3
+    achieved = alg_bytes / avg_s / 1e9
+    traffic = stored_traffic(w.name, C)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": "k_transport",
+                "kernel_us": round(avg_s * 1e6, 2), "algorithmic_bytes": alg_bytes}
+    flops = 2.0 * nnz * C
+    ai = flops / alg_bytes
+
+    # accuracy of this very output on a sample of rows + the CPU oracle time
+    Bh = B.cpu().numpy()
+    cpu = None
+    rel_err = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a sample of rows ...")
+        rows, ref, dt = cpu_baseline(w, L, th)
+        got = Bh[:, rows, :].astype(np.float64)
+        rel_err = float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+        cpu = {"value": round(len(rows) * w.n_out / dt, 3), "unit": "vertices/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{len(rows)} seeded output vertices x {w.n_out} configs of {w.name}, "
+                         f"O-B float64 (row precompute + transport), 1 thread, {dt:.1f}s"}
+        log(f"[bench] oracle {cpu['value']} vertices/s; GPU rel err on sample {rel_err:.3e}")
+
+    out = {
+        "metric": "shaded vertices/sec (K-term wavelet transport) at stated rel. err; % HBM peak",
+        "value": round(value, 1),
+        "unit": "vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.description}",
+            "n_vertices": w.n_vertices, "K": w.K, "n_keep": w.n_keep, "n_sh": w.n_sh,
+            "storage": w.storage, "lightings": w.n_light, "materials": w.n_cfg,
+            "columns": C, "backward": bool(args.backward), "tile": r.tile(),
+            "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),
+            "stage_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stage_ms.items()},
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    r.close()
+
+
+if __name__ == "__main__":
+    main()

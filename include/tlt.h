@@ -55,8 +55,10 @@ enum { TLT_F64 = 0, TLT_F32 = 1, TLT_BF16 = 2, TLT_F16 = 3 };
 enum { TLT_WAVELET_NONE = 0, TLT_WAVELET_HAAR = 1 };
 enum {
   TLT_SAVE_FOR_BACKWARD = 1, /* keep v_k[o,c] for render_backward */
-  TLT_FORCE_FULL = 2         /* recompute every stage, ignoring dirty flags */
+  TLT_FORCE_FULL = 2,        /* recompute every stage, ignoring dirty flags */
+  TLT_PLAIN_ROWS = 4         /* use the (column, value) row kernel even when tiles exist */
 };
+enum { TLT_LAYOUT_AUTO = 0, TLT_LAYOUT_ROWS = 1, TLT_LAYOUT_TILES = 2 };
 
 /*
  * Host-side geometry precompute (no GPU work).
@@ -139,6 +141,14 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  *   column is checked to lie in [0, n_cols) and rows to ascend, else
  *   TLT_E_FORMAT.
  * n_cols = n_pad (HAAR, n_pad = next power of two >= N) or N (NONE).
+ *
+ * Layout.  The rows are always kept as (column, value) pairs (the plain
+ * form).  Unless layout is ROWS or the storage is F64, the library also
+ * re-encodes them as block-dense tiles: V Morton-consecutive vertices
+ * (V*K rows, 64..128) share the sorted union of their kept columns and are
+ * stored densely over it (zeros where a row did not keep a column), in the
+ * operand order of the 16x16 matrix instructions.  Both layouts hold the
+ * same kept coefficients; render uses the tiles unless TLT_PLAIN_ROWS.
  * The library keeps its own device copies until tlt_destroy or the next
  * load_transport.  Material and lighting state are reset.
  */
@@ -161,6 +171,8 @@ typedef struct {
   const double *r_nodes;     /* [n_r] */
   const double *basis;       /* [K][n_r] */
   const double *mat_range;   /* [3][2] (lo, hi) of the PCA table, or NULL */
+  int32_t layout;            /* TLT_LAYOUT_*: AUTO = tiles for non-F64 storage */
+  int32_t tile_vertices;     /* vertices per tile block (0 = automatic) */
 } tlt_transport_desc;
 
 tlt_status tlt_create(tlt_ctx **out, int hip_device);
@@ -232,6 +244,19 @@ tlt_status tlt_read_state(tlt_ctx *ctx, int which, void *out, size_t *bytes,
  */
 tlt_status tlt_set_tile(tlt_ctx *ctx, int columns_per_lane);
 int tlt_get_tile(const tlt_ctx *ctx);
+
+/*
+ * Per-stage GPU timing.  While enabled, render and render_backward record a
+ * pair of HIP events on their stream around each stage: 0 = material
+ * weights g_k (Step 3), 1 = irradiance and its Haar transform (Step 1),
+ * 2 = wavelet transport with K-term fusion (Steps 2 and 4), 3 = adjoint
+ * reductions, 4 = material-only combine.  tlt_profile_enable(ctx, 1)
+ * clears the totals; tlt_profile_read waits for the recorded events and
+ * returns the summed elapsed milliseconds and the number of launches of a
+ * stage.  Do not enable during HIP graph capture.
+ */
+tlt_status tlt_profile_enable(tlt_ctx *ctx, int enable);
+tlt_status tlt_profile_read(tlt_ctx *ctx, int stage, double *total_ms, int64_t *launches);
 
 /* Library version string (static storage). */
 const char *tlt_version(void);

@@ -58,6 +58,28 @@ struct tlt_ctx {
   void *adj = nullptr;
   size_t adj_bytes = 0;
   bool v_valid = false;   // V holds v_k of the current lighting
+  int n_chunks = 0, ch_rows = 0;
+
+  // block-dense tiles (see tlt.h): offsets, union columns, values
+  bool tiles = false;
+  int tV = 0, tR = 0, t_blocks = 0;
+  int64_t *t_off = nullptr;
+  int32_t *t_ucol = nullptr;
+  void *t_val = nullptr;
+  size_t t_val_bytes = 0;
+
+  // transport partition: n_waves equal row ranges; split vertices cleared
+  int n_waves = 0;
+  int32_t *zero_v = nullptr;
+  int n_zero = 0;
+
+  // per-stage event timing
+  bool prof = false;
+  struct Ev { int stage; hipEvent_t a, b; };
+  std::vector<Ev> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[5] = {0, 0, 0, 0, 0};
+  int64_t prof_n[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -129,6 +151,13 @@ void free_all(tlt_ctx *c) {
   dfree(c->rn);
   dfree(c->basis);
   dfree(c->P);
+  dfree(c->zero_v);
+  c->n_zero = 0;
+  dfree(c->t_off);
+  dfree(c->t_ucol);
+  dfree(c->t_val);
+  c->tiles = false;
+  c->t_blocks = 0;
   c->have_P = false;
   c->loaded = false;
   c->sh = nullptr;
@@ -167,10 +196,117 @@ tlt_status ensure_columns(tlt_ctx *c) {
   HIPC(c, hipMemset(c->gcol, 0, e * (size_t)c->K * c->Cs));
   if ((s = dalloc(c, (void **)&c->g64, sizeof(double) * c->n_mat * 3 * c->K, "g")) != TLT_OK) return s;
   if ((s = dalloc(c, (void **)&c->dg64, sizeof(double) * c->n_mat * 9 * c->K, "dg")) != TLT_OK) return s;
+  c->ch_rows = ch_rows;
+  c->n_chunks = n_chunks;
   c->buf_nlight = c->n_light;
   c->buf_nmat = c->n_mat;
   c->mat_dirty = c->light_dirty = true;
   return TLT_OK;
+}
+
+PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
+  PrepArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.fp64 = c->fp64;
+  a.tdt = c->tdt;
+  a.Cs = Cs;
+  a.cols = cols;
+  a.rn = c->rn;
+  a.basis = c->basis;
+  a.nr = c->nr;
+  a.K = c->K;
+  a.T = c->T;
+  a.N = c->N;
+  a.n_sh = c->n_sh;
+  a.n_shp = c->n_shp;
+  a.area = c->area;
+  a.haar = c->wavelet == TLT_WAVELET_HAAR;
+  a.n_rows = c->n_rows;
+  a.ch_rows = std::min(c->n_rows, 256);
+  a.n_chunks = (c->n_rows + a.ch_rows - 1) / a.ch_rows;
+  return a;
+}
+
+// Equal row ranges per wave; vertices straddling two ranges are listed so
+// the prep launch can clear their outputs before the atomic completion.
+tlt_status ensure_partition(tlt_ctx *c) {
+  const char *e = std::getenv("TLT_WAVES_PER_CU");
+  const int wpc = (e && std::atoi(e) > 0) ? std::atoi(e) : 32;
+  const int nw = stream_waves(c->N, c->K, wpc);
+  if (nw == c->n_waves && (c->zero_v || c->n_zero == 0)) return TLT_OK;
+  dfree(c->zero_v);
+  c->n_zero = 0;
+  c->n_waves = nw;
+  const int64_t R = (int64_t)c->N * c->K, q = R / nw, rem = R % nw;
+  std::vector<int32_t> z;
+  for (int64_t w = 1; w < nw; ++w) {
+    const int64_t r0 = w * q + std::min<int64_t>(w, rem);
+    if (r0 % c->K) z.push_back((int32_t)(r0 / c->K));  // Morton position
+  }
+  if (z.empty()) return TLT_OK;
+  std::vector<int32_t> hp(c->N);
+  HIPC(c, hipMemcpy(hp.data(), c->perm, sizeof(int32_t) * c->N, hipMemcpyDeviceToHost));
+  for (auto &v : z) v = hp[v];                           // original vertex id
+  tlt_status s = dalloc(c, (void **)&c->zero_v, sizeof(int32_t) * z.size(), "split vertices");
+  if (s != TLT_OK) return s;
+  HIPC(c, hipMemcpy(c->zero_v, z.data(), sizeof(int32_t) * z.size(), hipMemcpyHostToDevice));
+  c->n_zero = (int)z.size();
+  return TLT_OK;
+}
+
+StreamArgs stream_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *gcol, void *B,
+                       void *vsave, int vs_stride) {
+  StreamArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.col = c->col;
+  a.val = c->val;
+  a.n_keep = (int)c->n_keep;
+  a.K = c->K;
+  a.N = c->N;
+  a.ehat = ehat;
+  a.Cs = Cs;
+  a.C = C;
+  a.gcol = gcol;
+  a.perm = c->perm;
+  a.B = B;
+  a.vsave = vsave;
+  a.vs_stride = vs_stride;
+  a.R = (int64_t)c->N * c->K;
+  a.n_waves = c->n_waves;
+  const char *e = std::getenv("TLT_STREAM_EPL");
+  a.epl = e ? std::atoi(e) : 0;
+  const char *nt = std::getenv("TLT_STREAM_NT");
+  a.nt = nt ? std::atoi(nt) : 1;
+  return a;
+}
+
+TileArgs tile_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *gcol, void *B,
+                   void *vsave, int vs_stride) {
+  TileArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.blk_off = c->t_off;
+  a.ucol = c->t_ucol;
+  a.val = c->t_val;
+  a.V = c->tV;
+  a.K = c->K;
+  a.R = c->tR;
+  a.n_blocks = c->t_blocks;
+  a.N = c->N;
+  a.ehat = ehat;
+  a.Cs = Cs;
+  a.C = C;
+  a.gcol = gcol;
+  a.perm = c->perm;
+  a.B = B;
+  a.vsave = vsave;
+  a.vs_stride = vs_stride;
+  return a;
+}
+
+int auto_tile_vertices(int K) {
+  for (int V : {32, 16, 8, 4, 64})
+    if (V * K >= 64 && V * K <= 128 && (V * K) % 16 == 0) return V;
+  return 0;
 }
 
 tlt_status ensure_V(tlt_ctx *c) {
@@ -188,24 +324,26 @@ tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   c->Psh = cplP;
   c->Gs = round_up(cplP, 16);
   const size_t e = c->esz;
-  void *Lm = nullptr, *G = nullptr, *part = nullptr, *gz = nullptr;
+  void *G = nullptr, *part = nullptr, *gz = nullptr;
   tlt_status s;
-  const int ch_rows = std::min(c->n_rows, 256);
-  const int n_chunks = (c->n_rows + ch_rows - 1) / ch_rows;
-  Cols ident{c->Gs, c->Gs / 3, 1, 1};
+  Cols ident{c->Psh, 1, 1, 1};
+  PrepArgs a = prep_args(c, c->Gs, ident);
   if ((s = dalloc(c, &c->P, e * (size_t)c->K * c->N * c->Psh, "P")) != TLT_OK) return s;
-  if ((s = dalloc(c, &Lm, e * c->n_shp * c->Gs, "identity lighting")) != TLT_OK) goto out;
   if ((s = dalloc(c, &G, e * (size_t)c->n_rows * c->Gs, "G")) != TLT_OK) goto out;
-  if ((s = dalloc(c, &part, e * (size_t)n_chunks * c->Gs, "G partials")) != TLT_OK) goto out;
+  if ((s = dalloc(c, &part, e * (size_t)a.n_chunks * c->Gs, "G partials")) != TLT_OK) goto out;
   if ((s = dalloc(c, &gz, e * (size_t)c->K * c->Gs, "zero weights")) != TLT_OK) goto out;
   {
+    a.n_tl_blocks = a.n_chunks * (c->Gs / 16);
+    a.sh = nullptr;  // identity lighting: column lm of G is Haar(pad(A o T[:, lm]))
+    a.ehat = G;
+    a.partial = part;
+    StreamArgs sa = stream_args(c, G, c->Gs, c->Psh, gz, nullptr, c->P, c->Psh);
     hipError_t he;
-    if ((he = hipMemsetAsync(gz, 0, e * (size_t)c->K * c->Gs, st)) != hipSuccess ||
-        (he = launch_lmat(nullptr, c->fp64, c->n_sh, c->n_shp, c->Gs, ident, Lm, st)) != hipSuccess ||
-        (he = launch_tl_haar(c->T, c->tdt, c->N, c->n_sh, c->n_shp, Lm, c->area, c->fp64,
-                             c->wavelet == TLT_WAVELET_HAAR, c->n_rows, c->Gs, G, part, st)) != hipSuccess ||
-        (he = launch_transport(c->col, c->val, c->vdt, c->n_keep, c->K, c->N, G, c->Gs, c->Psh,
-                               c->Psh, gz, c->perm, nullptr, c->P, c->Psh, c->fp64, st)) != hipSuccess ||
+    if ((he = hipMemset(gz, 0, e * (size_t)c->K * c->Gs)) != hipSuccess ||
+        (he = launch_prep(a, st)) != hipSuccess ||
+        (he = c->tiles ? launch_tiles(tile_args(c, G, c->Gs, c->Psh, nullptr, nullptr, c->P, c->Psh),
+                                      c->vdt, st)
+                       : launch_stream(sa, c->vdt, c->fp64, c->Psh, st)) != hipSuccess ||
         (he = hipStreamSynchronize(st)) != hipSuccess) {
       s = hip_fail(c, he, "building the lighting-transfer product");
       goto out;
@@ -214,11 +352,52 @@ tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   c->have_P = true;
   s = TLT_OK;
 out:
-  dfree(Lm);
   dfree(G);
   dfree(part);
   dfree(gz);
   return s;
+}
+
+// Stage timer: records an event pair around the launches of one stage.
+struct StageTimer {
+  tlt_ctx *c;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(tlt_ctx *c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
+    if (!c->prof) return;
+    a = take();
+    b = take();
+    if (a) (void)hipEventRecord(a, st);
+  }
+  hipEvent_t take() {
+    if (!c->pool.empty()) {
+      hipEvent_t e = c->pool.back();
+      c->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  ~StageTimer() {
+    if (!c->prof || !a || !b) return;
+    (void)hipEventRecord(b, st);
+    c->pending.push_back({stage, a, b});
+  }
+};
+
+void prof_drain(tlt_ctx *c) {
+  for (auto &e : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      c->prof_ms[e.stage] += ms;
+      c->prof_n[e.stage] += 1;
+    }
+    c->pool.push_back(e.a);
+    c->pool.push_back(e.b);
+  }
+  c->pending.clear();
 }
 
 float half_to_float(uint16_t h) {
@@ -284,6 +463,9 @@ void tlt_destroy(tlt_ctx *c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipDeviceSynchronize();
+  prof_drain(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  c->pool.clear();
   free_all(c);
   delete c;
 }
@@ -294,7 +476,7 @@ const char *tlt_last_error(const tlt_ctx *c) {
 
 tlt_status tlt_set_tile(tlt_ctx *c, int cpl) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
-  if (cpl != 0 && !transport_cpl_supported(cpl, c->fp64))
+  if (cpl != 0 && !stream_cpl_supported(cpl))
     return fail(&c->err, TLT_E_ARG, "unsupported columns_per_lane " + std::to_string(cpl));
   c->tile_req = cpl;
   return TLT_OK;
@@ -375,6 +557,13 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   tlt_status s;
   const size_t vsz = dtype_size(c->vdt);
   const size_t nnz = (size_t)n_rowsW * (size_t)d->n_keep;
+  const int tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K);
+  const bool tiles_ok = tV > 0 && tV * d->K >= 64 && tV * d->K <= 128 && (tV * d->K) % 16 == 0;
+  const bool want_tiles = !c->fp64 && d->layout != TLT_LAYOUT_ROWS && tiles_ok;
+  if (d->layout == TLT_LAYOUT_TILES && (c->fp64 || !tiles_ok)) {
+    s = fail(&c->err, TLT_E_ARG, "tiles need non-F64 storage and 64 <= V*K <= 128, V*K % 16 == 0");
+    goto fail_all;
+  }
   if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->val, vsz * nnz, "transport values")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->T, dtype_size(c->tdt) * (size_t)N * c->n_sh, "transfer")) != TLT_OK) goto fail_all;
@@ -413,40 +602,70 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
     };
     he = upload_q(d->transfer, c->T, c->tdt, (size_t)N * c->n_sh);
     if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transfer"); goto fail_all; }
-    if (d->col) {
-      he = hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
-      if (he == hipSuccess) he = hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice);
-      if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transport"); goto fail_all; }
-    } else {
-      // Build rows on the host in blocks of vertices, upload each block.
-      const int nth = host_threads();
-      const int64_t per_row = (int64_t)c->K * d->n_keep;
-      int64_t vb = std::max<int64_t>(1, (int64_t)(96 << 20) / std::max<int64_t>(1, per_row * 12));
-      vb = std::min<int64_t>(vb, N);
-      std::vector<int32_t> hc;
-      std::vector<double> hv;
-      try {
-        hc.resize((size_t)(vb * per_row));
-        hv.resize((size_t)(vb * per_row));
-      } catch (...) {
-        dfree(stage);
-        s = fail(&c->err, TLT_E_OOM, "host staging for the transport build");
-        goto fail_all;
-      }
-      for (int64_t o0 = 0; o0 < N; o0 += vb) {
-        const int64_t nv = std::min<int64_t>(vb, N - o0);
+    // Rows are built (or taken) in chunks of vertices; each chunk is uploaded
+    // as (column, value) rows and, when tiles are wanted, appended to them.
+    const int nth = host_threads();
+    const int64_t per_row = (int64_t)c->K * d->n_keep;
+    int64_t vb = std::max<int64_t>(1, (int64_t)(96 << 20) / std::max<int64_t>(1, per_row * 12));
+    if (want_tiles) vb = std::max<int64_t>(tV, vb / tV * tV);
+    vb = std::min<int64_t>(vb, N);
+    TileBuild tb;
+    tb.V = tV;
+    tb.K = c->K;
+    tb.kstep = tile_kstep(c->vdt);
+    std::vector<int32_t> hc;
+    std::vector<double> hv;
+    try {
+      if (!d->col) hc.resize((size_t)(vb * per_row));
+      if (!d->col || want_tiles) hv.resize((size_t)(vb * per_row));
+    } catch (...) {
+      dfree(stage);
+      s = fail(&c->err, TLT_E_OOM, "host staging for the transport build");
+      goto fail_all;
+    }
+    for (int64_t o0 = 0; o0 < N; o0 += vb) {
+      const int64_t nv = std::min<int64_t>(vb, N - o0);
+      const size_t off = (size_t)(o0 * per_row);
+      const size_t m = (size_t)(nv * per_row);
+      const int32_t *ccol;
+      if (d->col) {
+        ccol = d->col + off;
+        he = hipMemcpy(c->col + off, ccol, sizeof(int32_t) * m, hipMemcpyHostToDevice);
+        if (he == hipSuccess)
+          he = hipMemcpy((char *)c->val + off * vsz, (const char *)d->val + off * vsz, vsz * m,
+                         hipMemcpyHostToDevice);
+        if (want_tiles)
+          for (size_t e = 0; e < m; ++e) hv[e] = widen(d->val, c->vdt, off + e);
+      } else {
         host_build_rows((int)nv, n_cols, c->K, c->nr, c->wavelet, d->n_keep, d->position + 3 * o0,
                         d->r_nodes, d->basis, hc.data(), hv.data(), nth, N, d->position);
-        const size_t off = (size_t)(o0 * per_row);
-        const size_t m = (size_t)(nv * per_row);
+        ccol = hc.data();
         he = hipMemcpy(c->col + off, hc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice);
         if (he == hipSuccess) he = upload_q(hv.data(), (char *)c->val + off * vsz, c->vdt, m);
-        if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading built transport"); goto fail_all; }
       }
+      if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading the transport"); goto fail_all; }
+      if (want_tiles) tiles_append(tb, (int)nv, n_cols, d->n_keep, ccol, hv.data(), c->vdt, nth);
     }
     dfree(stage);
+    if (want_tiles) {
+      c->tiles = true;
+      c->tV = tV;
+      c->tR = tV * c->K;
+      c->t_blocks = (int)tb.n_blocks;
+      const size_t nu = tb.ucol.size();
+      const size_t nvals = nu * (size_t)c->tR;
+      c->t_val_bytes = nvals * (c->vdt == TLT_F32 ? 4 : 2);
+      if ((s = dalloc(c, (void **)&c->t_off, sizeof(int64_t) * tb.blk_off.size(), "tile offsets")) != TLT_OK) goto fail_all;
+      if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * nu, "tile columns")) != TLT_OK) goto fail_all;
+      if ((s = dalloc(c, &c->t_val, c->t_val_bytes, "tile values")) != TLT_OK) goto fail_all;
+      HTRY(hipMemcpy(c->t_off, tb.blk_off.data(), sizeof(int64_t) * tb.blk_off.size(), hipMemcpyHostToDevice));
+      HTRY(hipMemcpy(c->t_ucol, tb.ucol.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice));
+      HTRY(hipMemcpy(c->t_val, c->vdt == TLT_F32 ? (const void *)tb.v32.data() : (const void *)tb.v16.data(),
+                     c->t_val_bytes, hipMemcpyHostToDevice));
+    }
 #undef HTRY
   }
+  if ((s = ensure_partition(c)) != TLT_OK) goto fail_all;
   if ((s = ensure_P(c, 0)) != TLT_OK) goto fail_all;
   c->loaded = true;
   c->mat_dirty = c->light_dirty = true;
@@ -506,27 +725,59 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (!B) return fail(&c->err, TLT_E_ARG, "B is NULL");
   if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
     return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
-  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL)) return fail(&c->err, TLT_E_ARG, "unknown flags");
+  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS))
+    return fail(&c->err, TLT_E_ARG, "unknown flags");
   hipStream_t st = (hipStream_t)stream;
   tlt_status s;
   if ((s = ensure_columns(c)) != TLT_OK) return s;
   const bool save = flags & TLT_SAVE_FOR_BACKWARD;
   const bool full = flags & TLT_FORCE_FULL;
+  const bool use_tiles = c->tiles && !(flags & TLT_PLAIN_ROWS);
   if (save && (s = ensure_V(c)) != TLT_OK) return s;
   Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
-  if (c->mat_dirty || full)
-    HIPC(c, launch_gk(c->theta, c->rn, c->basis, c->nr, c->K, c->g64, c->dg64, c->gcol, c->fp64,
-                      c->Cs, cols, st));
+  const bool do_gk = c->mat_dirty || full;
   const bool relight = c->light_dirty || full || !(c->v_valid);
+  PrepArgs a = prep_args(c, c->Cs, cols);
+  if (do_gk) {
+    a.n_gk_blocks = c->n_mat * 3;
+    a.theta = c->theta;
+    a.g64 = c->g64;
+    a.dg64 = c->dg64;
+    a.gcol = c->gcol;
+  }
   if (!relight && c->V) {
     // material-only edit: reuse the saved per-term transport v_k
+    if (do_gk) {
+      StageTimer t(c, 0, st);
+      HIPC(c, launch_prep(a, st));
+    }
+    StageTimer t(c, 4, st);
     HIPC(c, launch_combine(c->V, c->Cs, c->gcol, c->K, c->N, c->C, c->perm, B, c->fp64, st));
   } else {
-    HIPC(c, launch_lmat(c->sh, c->fp64, c->n_sh, c->n_shp, c->Cs, cols, c->Lm, st));
-    HIPC(c, launch_tl_haar(c->T, c->tdt, c->N, c->n_sh, c->n_shp, c->Lm, c->area, c->fp64,
-                           c->wavelet == TLT_WAVELET_HAAR, c->n_rows, c->Cs, c->ehat, c->partial, st));
-    HIPC(c, launch_transport(c->col, c->val, c->vdt, c->n_keep, c->K, c->N, c->ehat, c->Cs, c->C,
-                             c->cpl, c->gcol, c->perm, B, save ? c->V : nullptr, c->Cs, c->fp64, st));
+    a.n_tl_blocks = c->n_chunks * (c->Cs / 16);
+    a.sh = c->sh;
+    a.ehat = c->ehat;
+    a.partial = c->partial;
+    if (c->n_zero > 0 && !use_tiles) {
+      a.B = B;
+      a.zero_v = c->zero_v;
+      a.n_zero = c->n_zero;
+      a.n_zero_blocks = std::max(1, std::min(64, (c->n_zero * c->C + 255) / 256));
+    }
+    {
+      StageTimer t(c, 1, st);
+      HIPC(c, launch_prep(a, st));
+    }
+    {
+      StageTimer t(c, 2, st);
+      if (use_tiles) {
+        HIPC(c, launch_tiles(tile_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs),
+                             c->vdt, st));
+      } else {
+        StreamArgs sa = stream_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs);
+        HIPC(c, launch_stream(sa, c->vdt, c->fp64, c->cpl, st));
+      }
+    }
     c->v_valid = save;
   }
   c->mat_dirty = false;
@@ -550,8 +801,29 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
     c->adj_bytes = need;
   }
   Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
+  StageTimer t(c, 3, st);
   HIPC(c, launch_adjoint(dB, c->V, c->Cs, c->P, c->Psh, c->gcol, c->dg64, c->perm, c->N, c->K,
                          c->n_sh, cols, c->fp64, c->adj, c->adj_bytes, dSH, dTheta, st));
+  return TLT_OK;
+}
+
+tlt_status tlt_profile_enable(tlt_ctx *c, int enable) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  prof_drain(c);
+  for (int i = 0; i < 5; ++i) {
+    c->prof_ms[i] = 0.0;
+    c->prof_n[i] = 0;
+  }
+  c->prof = enable != 0;
+  return TLT_OK;
+}
+
+tlt_status tlt_profile_read(tlt_ctx *c, int stage, double *total_ms, int64_t *launches) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (stage < 0 || stage > 4) return fail(&c->err, TLT_E_ARG, "stage must be in 0..4");
+  prof_drain(c);
+  if (total_ms) *total_ms = c->prof_ms[stage];
+  if (launches) *launches = c->prof_n[stage];
   return TLT_OK;
 }
 

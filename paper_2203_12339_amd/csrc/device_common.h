@@ -1,0 +1,80 @@
+// Device helpers shared by the gfx950 kernels (wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace tlt {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Storage loads: every storage type widens exactly to the compute type.
+template <typename VT, typename CT> __device__ __forceinline__ CT ld(const VT *p, int64_t i);
+template <> __device__ __forceinline__ double ld<double, double>(const double *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<float, float>(const float *p, int64_t i) { return p[i]; }
+template <> __device__ __forceinline__ float ld<bf16s, float>(const bf16s *p, int64_t i) {
+  return __uint_as_float(((uint32_t)p[i].u) << 16);
+}
+template <> __device__ __forceinline__ float ld<f16s, float>(const f16s *p, int64_t i) {
+  return (float)__builtin_bit_cast(_Float16, p[i].u);
+}
+
+// Streaming (non-temporal) loads of the transport: read once per render,
+// kept out of the way of the gathered irradiance rows in L2.
+template <typename VT, typename CT> __device__ __forceinline__ CT ld_nt(const VT *p, int64_t i);
+template <> __device__ __forceinline__ double ld_nt<double, double>(const double *p, int64_t i) {
+  return __builtin_nontemporal_load(p + i);
+}
+template <> __device__ __forceinline__ float ld_nt<float, float>(const float *p, int64_t i) {
+  return __builtin_nontemporal_load(p + i);
+}
+template <> __device__ __forceinline__ float ld_nt<bf16s, float>(const bf16s *p, int64_t i) {
+  const uint16_t u = __builtin_nontemporal_load(&p[i].u);
+  return __uint_as_float(((uint32_t)u) << 16);
+}
+template <> __device__ __forceinline__ float ld_nt<f16s, float>(const f16s *p, int64_t i) {
+  const uint16_t u = __builtin_nontemporal_load(&p[i].u);
+  return (float)__builtin_bit_cast(_Float16, u);
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// Contiguous row load of CPL compute-type values (16-byte vector loads).
+template <typename CT, int CPL> struct RowLoad;
+template <int CPL> struct RowLoad<float, CPL> {
+  static __device__ __forceinline__ void load(const float *p, float (&v)[CPL]) {
+    static_assert(CPL % 4 == 0, "float rows load as float4");
+#pragma unroll
+    for (int q = 0; q < CPL / 4; ++q) {
+      const float4 t = reinterpret_cast<const float4 *>(p)[q];
+      v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+    }
+  }
+};
+template <int CPL> struct RowLoad<double, CPL> {
+  static __device__ __forceinline__ void load(const double *p, double (&v)[CPL]) {
+    static_assert(CPL % 2 == 0, "double rows load as double2");
+#pragma unroll
+    for (int q = 0; q < CPL / 2; ++q) {
+      const double2 t = reinterpret_cast<const double2 *>(p)[q];
+      v[2 * q] = t.x; v[2 * q + 1] = t.y;
+    }
+  }
+};
+
+// Hardware workgroup b runs on XCD b % 8: remap so that each XCD gets a
+// contiguous range of logical blocks (neighbouring vertices share L2 lines).
+__device__ __forceinline__ int xcd_remap(int b, int n_logical) {
+  const int per = (n_logical + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace tlt

@@ -1,0 +1,349 @@
+// Per-frame preparation in ONE launch (heterogeneous workgroups):
+//
+//   [0, n_gk)              a1: material weights g_k and dg_k/dtheta (float64),
+//                              rendering Step 3 of Sec. 4 with Eq. (4);
+//   [n_gk, n_gk + n_tl)    a2+a3: E = T L on MFMA, times area, Haar levels
+//                              inside a 256-row chunk (Step 1, Eq. 6 and 8);
+//   [.., + n_zero)         clears B at the vertices whose rows the
+//                              transport kernel splits between two waves.
+//
+// A second small launch (k_haar_top) runs the coarse Haar levels over the
+// chunk sums.
+//
+// MFMA 16x16x4 operand layout (f32 and f64 alike): lane l supplies
+// A[l%16][l/16] and B[l/16][l%16].  Result element v of lane l is
+// D[4*(l/16)+v][l%16] for f32 but D[(l/16)+4v][l%16] for f64 (checked on
+// gfx950 with a probe of known operands).
+
+#include <algorithm>
+
+#include "device_common.h"
+
+namespace tlt {
+
+// ---------------------------------------------------------------------------
+// a1: dipole R_d (Eq. 4) with its parameter derivatives.
+// ---------------------------------------------------------------------------
+
+struct RdGrad {
+  double R, da, ds, de;
+};
+
+__device__ inline void pole(double z, double d, double s, double &f, double &fs, double &fz) {
+  const double e = exp(-s * d);
+  const double id = 1.0 / d;
+  const double h = (s + id) * e * id * id;
+  f = z * h;
+  fs = -s * z * e * id;  // partial w.r.t. sigma_tr
+  const double hp = -e * id * id * (s * s + 3.0 * s * id + 3.0 * id * id);
+  fz = h + z * hp * (z * id);  // total w.r.t. z through d = sqrt(r^2 + z^2)
+}
+
+__device__ inline RdGrad rd_grad(double r, double sa, double ss, double eta) {
+  const double st = sa + ss;
+  const double alpha = ss / st;
+  const double s = sqrt(3.0 * sa * st);
+  const double zr = 1.0 / st;
+  const double f = -1.440 / (eta * eta) + 0.710 / eta + 0.668 + 0.0636 * eta;
+  const double A = (1.0 + f) / (1.0 - f);
+  const double cv = 1.0 + 4.0 * A / 3.0;
+  const double zv = zr * cv;
+  const double dr = sqrt(r * r + zr * zr);
+  const double dv = sqrt(r * r + zv * zv);
+  double fr, frs, frz, fv, fvs, fvz;
+  pole(zr, dr, s, fr, frs, frz);
+  pole(zv, dv, s, fv, fvs, fvz);
+  const double S = fr + fv;
+  const double k4 = 1.0 / (4.0 * M_PI);
+  const double dfd = 2.880 / (eta * eta * eta) - 0.710 / (eta * eta) + 0.0636;
+  const double dA = 2.0 / ((1.0 - f) * (1.0 - f)) * dfd;
+  const double dzr = -1.0 / (st * st);
+  RdGrad g;
+  g.R = alpha * k4 * S;
+  {
+    const double dal = -ss / (st * st), dsg = 3.0 * (st + sa) / (2.0 * s);
+    g.da = dal * k4 * S + alpha * k4 * ((frs + fvs) * dsg + frz * dzr + fvz * cv * dzr);
+  }
+  {
+    const double dal = sa / (st * st), dsg = 3.0 * sa / (2.0 * s);
+    g.ds = dal * k4 * S + alpha * k4 * ((frs + fvs) * dsg + frz * dzr + fvz * cv * dzr);
+  }
+  g.de = alpha * k4 * fvz * (zr * 4.0 / 3.0 * dA);
+  return g;
+}
+
+__device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
+  // smem: q[4][nr] (R_d and its three partials on the nodes), red[4][K][4]
+  double *q = smem;
+  double *red = smem + 4 * (size_t)a.nr;
+  const int m = mc / 3, ch = mc % 3;
+  const double sa = a.theta[mc * 3 + 0], ss = a.theta[mc * 3 + 1], eta = a.theta[mc * 3 + 2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int n = threadIdx.x; n < a.nr; n += 256) {
+    const RdGrad g = rd_grad(a.rn[n], sa, ss, eta);
+    q[n] = g.R;
+    q[a.nr + n] = g.da;
+    q[2 * a.nr + n] = g.ds;
+    q[3 * a.nr + n] = g.de;
+  }
+  __syncthreads();
+  // projections on b_k: per-thread partial sums over its nodes, one wave
+  // reduction, then a fixed-order sum over the four waves.
+  for (int k = 0; k < a.K; ++k) {
+    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    for (int n = threadIdx.x; n < a.nr; n += 256) {
+      const double b = a.basis[(size_t)k * a.nr + n];
+      p0 = fma(q[n], b, p0);
+      p1 = fma(q[a.nr + n], b, p1);
+      p2 = fma(q[2 * a.nr + n], b, p2);
+      p3 = fma(q[3 * a.nr + n], b, p3);
+    }
+    p0 = wave_sum(p0);
+    p1 = wave_sum(p1);
+    p2 = wave_sum(p2);
+    p3 = wave_sum(p3);
+    if (lane == 0) {
+      double *r = red + ((size_t)wave * a.K + k) * 4;
+      r[0] = p0; r[1] = p1; r[2] = p2; r[3] = p3;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 4 * a.K; t += 256) {
+    const int k = t / 4, qn = t % 4;
+    double acc = 0.0;
+    for (int w = 0; w < 4; ++w) acc += red[((size_t)w * a.K + k) * 4 + qn];
+    if (qn == 0) {
+      a.g64[(size_t)mc * a.K + k] = acc;
+      for (int o = 0; o < a.cols.n_out; ++o) {
+        const int mo = a.cols.n_mat > 1 ? o : 0;
+        if (mo != m) continue;
+        const int c = 3 * o + ch;
+        if (a.fp64)
+          ((double *)a.gcol)[(size_t)k * a.Cs + c] = acc;
+        else
+          ((float *)a.gcol)[(size_t)k * a.Cs + c] = (float)acc;
+      }
+    } else {
+      a.dg64[((size_t)mc * a.K + k) * 3 + (qn - 1)] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2 + a3.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename CT> struct MfmaOut;
+template <> struct MfmaOut<float> {
+  typedef f32x4 V4;
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct MfmaOut<double> {
+  typedef f64x4 V4;
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+
+constexpr int TL_CH = 256;
+constexpr int TL_STRIDE = 17;
+
+template <typename TT, typename CT>
+__device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
+  typedef typename MfmaOut<CT>::V4 V4;
+  CT *x = reinterpret_cast<CT *>(smem);
+  const int chunk = t % a.n_chunks;
+  const int ctile = t / a.n_chunks;
+  const int c0 = ctile * 16;
+  const int i0 = chunk * a.ch_rows;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const TT *T = (const TT *)a.T;
+  const CT *sh = (const CT *)a.sh;
+  const CT *area = (const CT *)a.area;
+  CT *ehat = (CT *)a.ehat;
+  CT *partial = (CT *)a.partial;
+
+  // lighting column of this lane (B operand column n = li)
+  const int c = c0 + li;
+  int sh_base = -1;
+  if (sh != nullptr && c < a.cols.C) {
+    const int q = c / 3, ch = c - 3 * q;
+    const int l = a.cols.n_light > 1 ? q : 0;
+    sh_base = (l * a.n_sh) * 3 + ch;
+  }
+  if (64 * wave < a.ch_rows) {
+    V4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = V4{0, 0, 0, 0};
+    for (int kk = 0; kk < a.n_shp; kk += 4) {
+      const int kc = kk + lk;
+      CT b = 0;
+      if (kc < a.n_sh) {
+        if (sh == nullptr)
+          b = (kc == c) ? CT(1) : CT(0);
+        else if (sh_base >= 0)
+          b = sh[sh_base + kc * 3];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int r = i0 + 64 * wave + 16 * u + li;
+        CT av = 0;
+        if (r < a.N && kc < a.n_sh && 64 * wave + 16 * u < a.ch_rows)
+          av = ld<TT, CT>(T, (int64_t)r * a.n_sh + kc);
+        acc[u] = mfma16(av, b, acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int lr = 64 * wave + 16 * u + MfmaOut<CT>::row(lk, v);
+        const int r = i0 + lr;
+        const CT ar = (r < a.N) ? area[r] : CT(0);
+        if (lr < a.ch_rows) x[lr * TL_STRIDE + li] = acc[u][v] * ar;
+      }
+    }
+  }
+  __syncthreads();
+
+  if (!a.haar) {
+    for (int idx = threadIdx.x; idx < a.ch_rows * 16; idx += 256) {
+      const int lr = idx >> 4, cc = idx & 15;
+      const int r = i0 + lr;
+      if (r < a.n_rows) ehat[(size_t)r * a.Cs + c0 + cc] = x[lr * TL_STRIDE + cc];
+    }
+    return;
+  }
+
+  const CT h = CT(0.70710678118654752440);
+  for (int len = a.ch_rows; len > 1; len >>= 1) {
+    const int half = len >> 1;
+    CT sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      if (idx < half * 16) {
+        const int i = idx >> 4, cc = idx & 15;
+        const CT p = x[(2 * i) * TL_STRIDE + cc];
+        const CT q = x[(2 * i + 1) * TL_STRIDE + cc];
+        const int64_t j = (int64_t)half * (a.n_chunks + chunk) + i;
+        ehat[j * a.Cs + c0 + cc] = (p - q) * h;
+        sv[u] = (p + q) * h;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = threadIdx.x + 256 * u;
+      if (idx < half * 16) x[(idx >> 4) * TL_STRIDE + (idx & 15)] = sv[u];
+    }
+    __syncthreads();
+  }
+  if (a.n_chunks == 1) {
+    if (threadIdx.x < 16) ehat[c0 + threadIdx.x] = x[threadIdx.x];
+    return;
+  }
+  if (threadIdx.x < 16) partial[(size_t)chunk * a.Cs + c0 + threadIdx.x] = x[threadIdx.x];
+}
+
+// Coarse Haar levels over the n_chunks chunk sums of one column (a second,
+// small launch: the chunk sums come from every XCD, and a kernel boundary
+// is the cheap way to make them visible).  grid: Cs workgroups.
+template <typename CT>
+__global__ __launch_bounds__(256) void k_haar_top(const CT *__restrict__ partial, int n_chunks,
+                                                  int Cs, CT *__restrict__ ehat) {
+  extern __shared__ __align__(16) unsigned char raw[];
+  CT *s0 = reinterpret_cast<CT *>(raw);
+  CT *s1 = s0 + n_chunks;
+  const int c = blockIdx.x;
+  for (int i = threadIdx.x; i < n_chunks; i += 256) s0[i] = partial[(size_t)i * Cs + c];
+  __syncthreads();
+  const CT h = CT(0.70710678118654752440);
+  CT *src = s0, *dst = s1;
+  for (int len = n_chunks; len > 1; len >>= 1) {
+    const int half = len >> 1;
+    for (int i = threadIdx.x; i < half; i += 256) {
+      const CT p = src[2 * i], q = src[2 * i + 1];
+      ehat[(size_t)(half + i) * Cs + c] = (p - q) * h;
+      dst[i] = (p + q) * h;
+    }
+    __syncthreads();
+    CT *t = src;
+    src = dst;
+    dst = t;
+  }
+  if (threadIdx.x == 0) ehat[c] = src[0];
+}
+
+template <typename CT>
+__device__ void zero_block(const PrepArgs &a, int t) {
+  CT *B = (CT *)a.B;
+  const int64_t n = (int64_t)a.n_zero * a.cols.C;
+  for (int64_t idx = (int64_t)t * 256 + threadIdx.x; idx < n; idx += (int64_t)a.n_zero_blocks * 256) {
+    const int v = (int)(idx / a.cols.C), c = (int)(idx % a.cols.C);
+    const int q = c / 3, ch = c - 3 * q;
+    B[((int64_t)q * a.N + a.zero_v[v]) * 3 + ch] = CT(0);
+  }
+}
+
+template <typename TT, typename CT>
+__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int b = blockIdx.x;
+  if (b < a.n_gk_blocks) {
+    gk_block(a, b, reinterpret_cast<double *>(smem));
+    return;
+  }
+  b -= a.n_gk_blocks;
+  if (b < a.n_tl_blocks) {
+    tl_block<TT, CT>(a, b, smem);
+    return;
+  }
+  b -= a.n_tl_blocks;
+  zero_block<CT>(a, b);
+}
+
+size_t prep_lds_bytes(const PrepArgs &a) {
+  const size_t esz = a.fp64 ? 8 : 4;
+  size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // a1
+  s = std::max(s, (size_t)TL_CH * TL_STRIDE * esz);
+  return s;
+}
+
+hipError_t launch_prep(const PrepArgs &a, hipStream_t st) {
+  const int blocks = a.n_gk_blocks + a.n_tl_blocks + a.n_zero_blocks;
+  if (blocks == 0) return hipSuccess;
+  const size_t lds = prep_lds_bytes(a);
+  if (a.fp64) {
+    if (a.tdt != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_prep<double, double>), dim3(blocks), dim3(256), lds, st, a);
+  } else {
+    switch (a.tdt) {
+      case 1: hipLaunchKernelGGL((k_prep<float, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      case 2: hipLaunchKernelGGL((k_prep<bf16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      case 3: hipLaunchKernelGGL((k_prep<f16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (a.n_tl_blocks > 0 && a.haar && a.n_chunks > 1) {
+    const size_t lds2 = (size_t)a.n_chunks * 3 / 2 * (a.fp64 ? 8 : 4);
+    if (a.fp64)
+      hipLaunchKernelGGL((k_haar_top<double>), dim3(a.Cs), dim3(256), lds2, st,
+                         (const double *)a.partial, a.n_chunks, a.Cs, (double *)a.ehat);
+    else
+      hipLaunchKernelGGL((k_haar_top<float>), dim3(a.Cs), dim3(256), lds2, st,
+                         (const float *)a.partial, a.n_chunks, a.Cs, (float *)a.ehat);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace tlt

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 namespace tlt {
@@ -10,7 +11,8 @@ namespace tlt {
 struct bf16s { uint16_t u; };
 struct f16s { uint16_t u; };
 
-// Column mapping of a launch: column c = 3*q + ch of output set q.
+// Column mapping of a launch: column c = 3*q + ch of output set q uses
+// lighting (n_light > 1 ? q : 0) and material (n_mat > 1 ? q : 0).
 struct Cols {
   int C;        // 3 * n_out
   int n_out;
@@ -18,31 +20,79 @@ struct Cols {
   int n_mat;
 };
 
-// a1: g[m][ch][k], dg[m][ch][k][p] in float64 and the per-column weights
-// gcol[k][Cs] (compute precision, zero for padded columns).
-hipError_t launch_gk(const double *theta, const double *rn, const double *basis, int nr, int K,
-                     double *g64, double *dg64, void *gcol, bool fp64, int Cs, Cols cols,
-                     hipStream_t st);
+// One launch for a1 (material weights), a2+a3 (irradiance and its Haar
+// transform) and the clearing of split output vertices; any part may be
+// switched off by a zero block count.
+struct PrepArgs {
+  bool fp64;
+  int tdt;                 // transfer storage (tlt.h codes)
+  int Cs;                  // column stride of Ehat and gcol
+  Cols cols;
+  // a1
+  int n_gk_blocks;         // n_mat * 3, or 0
+  const double *theta;     // [n_mat][3][3]
+  const double *rn;        // [nr]
+  const double *basis;     // [K][nr]
+  int nr, K;
+  double *g64, *dg64;      // [n_mat][3][K], [n_mat][3][K][3]
+  void *gcol;              // [K][Cs] compute precision
+  // a2 + a3
+  int n_tl_blocks;         // n_chunks * Cs/16, or 0
+  const void *T;           // [N][n_sh] storage tdt
+  int N, n_sh, n_shp;
+  const void *sh;          // [n_light][n_sh][3] compute precision; nullptr = identity
+  const void *area;        // [N] compute precision
+  int haar, ch_rows, n_rows, n_chunks;
+  void *ehat;              // [n_rows][Cs]
+  void *partial;           // [n_chunks][Cs]
+  // clearing of B at split vertices
+  int n_zero_blocks;
+  void *B;                 // [n_out][N][3]
+  const int32_t *zero_v;   // original vertex ids
+  int n_zero;
+};
+hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
+size_t prep_lds_bytes(const PrepArgs &a);
 
-// Lighting matrix Lm[lm][Cs] (compute precision) from sh [n_light][n_sh][3];
-// identity (Lm[lm][lm] = 1) when sh == nullptr.  Rows up to n_shp.
-hipError_t launch_lmat(const void *sh, bool fp64, int n_sh, int n_shp, int Cs, Cols cols,
-                       void *Lm, hipStream_t st);
+// a4 + a5: streamed wavelet-sparse transport with K-term fusion.
+struct StreamArgs {
+  const int32_t *col;      // [N*K][n_keep]
+  const void *val;         // [N*K][n_keep] storage
+  int n_keep, K, N;
+  const void *ehat;        // [n_rows][Cs]
+  int Cs, C;
+  const void *gcol;        // [K][Cs]
+  const int32_t *perm;     // [N]
+  void *B;                 // [n_out][N][3] or nullptr
+  void *vsave;             // [K][N][vs_stride] or nullptr
+  int vs_stride;
+  int64_t R;               // N*K rows
+  int n_waves;             // <= N
+  int n_logical_blocks;    // set by launch_stream
+  int epl;                 // entries per lane and step for 4-column tiles (0 = 8)
+  int nt;                  // non-temporal loads of the transport
+};
+hipError_t launch_stream(StreamArgs a, int vdt, bool fp64, int cpl, hipStream_t st);
+bool stream_cpl_supported(int cpl);
+int stream_waves(int N, int K, int waves_per_cu);
 
-// a2 + a3: Ehat = Haar(pad(A o (T Lm))) over rows (wavelet) or A o (T Lm).
-// T [N][n_sh] storage tdt; area [N] (compute precision); ehat [n_rows][Cs];
-// partial [n_chunks][Cs] scratch for the coarse levels.
-hipError_t launch_tl_haar(const void *T, int tdt, int N, int n_sh, int n_shp, const void *Lm,
-                          const void *area, bool fp64, bool haar, int n_rows, int Cs,
-                          void *ehat, void *partial, hipStream_t st);
-
-// a4 + a5: B[q][perm[o]][ch] = sum_k gcol[k][c] sum_j W[o*K+k][j] ehat[j][c]
-// and optionally vsave[k][o][vs_stride] = per-k sums. B may be null.
-hipError_t launch_transport(const int32_t *col, const void *val, int vdt, int64_t n_keep, int K,
-                            int N, const void *ehat, int Cs, int C, int cpl, const void *gcol,
-                            const int32_t *perm, void *B, void *vsave, int vs_stride, bool fp64,
-                            hipStream_t st);
-bool transport_cpl_supported(int cpl, bool fp64);
+// a4 + a5 on block-dense tiles (16-bit or f32 storage, f32 compute).
+struct TileArgs {
+  const int64_t *blk_off;  // [n_blocks+1] union offsets
+  const int32_t *ucol;     // union column ids
+  const void *val;         // fragment-ordered values
+  int V, K, R, n_blocks, N;
+  const void *ehat;        // [n_rows][Cs] float32
+  int Cs, C;
+  const void *gcol;        // [K][Cs] float32, or nullptr with B == nullptr
+  const int32_t *perm;
+  void *B;                 // [n_out][N][3] float32 or nullptr
+  void *vsave;             // [K][N][vs_stride] or nullptr
+  int vs_stride;
+  int wn, kc;              // set by launch_tiles: waves along columns, k-steps per chunk
+};
+hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
+int tile_kstep(int vdt);
 
 // Material-only update: B from saved v_k [K][N][Cs] and gcol.
 hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
@@ -55,7 +105,7 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
                           void *dSH, double *dTheta, hipStream_t st);
 size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64);
 
-// Storage conversion of float64 host values to device storage type.
+// Storage conversion of float64 values to device storage type.
 hipError_t launch_quantize(const double *src, void *dst, int vdt, int64_t n, hipStream_t st);
 
 }  // namespace tlt

@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libtlt.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 WAVELET_NONE, WAVELET_HAAR = 0, 1
-SAVE_FOR_BACKWARD, FORCE_FULL = 1, 2
+SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS = 1, 2, 4
+LAYOUTS = {"auto": 0, "rows": 1, "tiles": 2}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
 OK = 0
@@ -56,7 +57,7 @@ class TransportDesc(ctypes.Structure):
         ("n_keep", ctypes.c_int64),
         ("col", _i32p), ("val", _p), ("position", _f64p), ("transfer", _f64p),
         ("area", _f64p), ("perm", _i32p), ("r_nodes", _f64p), ("basis", _f64p),
-        ("mat_range", _f64p),
+        ("mat_range", _f64p), ("layout", ctypes.c_int32), ("tile_vertices", ctypes.c_int32),
     ]
 
 
@@ -83,13 +84,17 @@ _read_state = _sig("tlt_read_state", ctypes.c_int, _p, ctypes.c_int, _p,
 _set_tile = _sig("tlt_set_tile", ctypes.c_int, _p, ctypes.c_int)
 _get_tile = _sig("tlt_get_tile", ctypes.c_int, _p)
 _version = _sig("tlt_version", ctypes.c_char_p)
+_profile_enable = _sig("tlt_profile_enable", ctypes.c_int, _p, ctypes.c_int)
+_profile_read = _sig("tlt_profile_read", ctypes.c_int, _p, ctypes.c_int,
+                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64))
 _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, _f64p, _f64p, _f64p,
                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
 
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
-            "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version"]
+            "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
+            "tlt_profile_enable", "tlt_profile_read"]
 
 
 class TltError(RuntimeError):
@@ -206,7 +211,8 @@ class Renderer:
         return _last_error(self._h).decode(errors="replace")
 
     # -- transport --------------------------------------------------------
-    def load_transport(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None):
+    def load_transport(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None,
+                       layout="auto", tile_vertices=0):
         N = scene["perm"].shape[0]
         n_pad = 1 << (N - 1).bit_length()
         vdt = DTYPES[storage]
@@ -229,6 +235,8 @@ class Renderer:
         d.value_dtype = vdt
         d.transfer_dtype = vdt
         d.n_keep = self.n_keep
+        d.layout = LAYOUTS[layout]
+        d.tile_vertices = int(tile_vertices)
         if col is not None:
             col = np.ascontiguousarray(col, dtype=np.int32)
             d.col = _ptr(col, ctypes.c_int32)
@@ -273,12 +281,13 @@ class Renderer:
         import torch
         return torch.float64 if self.fp64 else torch.float32
 
-    def render(self, out=None, save=False, force=False):
+    def render(self, out=None, save=False, force=False, plain=False):
         import torch
         if out is None:
             out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
                               device=self.torch_device)
-        flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0)
+        flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0) | \
+            (PLAIN_ROWS if plain else 0)
         _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags), self._h)
         return out
 
@@ -332,6 +341,18 @@ class Renderer:
     def dg(self):
         buf, _ = self.read_state(2)
         return buf.view(np.float64).reshape(self.n_mat, 3, self.K, 3)
+
+    STAGES = {"weights": 0, "irradiance": 1, "transport": 2, "adjoint": 3, "combine": 4}
+
+    def profile(self, enable=True):
+        _check(_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self, stage):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(_profile_read(self._h, self.STAGES.get(stage, stage), ctypes.byref(ms),
+                             ctypes.byref(n)), self._h)
+        return ms.value, n.value
 
     def set_tile(self, cpl: int):
         _check(_set_tile(self._h, int(cpl)), self._h)

@@ -16,10 +16,12 @@ def scene_for(w: synth.Workload, K=None):
                          synth.MATERIAL_GRID)
 
 
-def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None) -> Renderer:
+def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout="auto",
+                 tile_vertices=0) -> Renderer:
     sc = scene_for(w, K) if scene is None else scene
     r = Renderer(device)
-    r.load_transport(sc, w.n_keep, storage=w.storage, wavelet=w.wavelet)
+    r.load_transport(sc, w.n_keep, storage=w.storage, wavelet=w.wavelet, layout=layout,
+                     tile_vertices=tile_vertices)
     r.scene = sc
     r.workload = w
     return r

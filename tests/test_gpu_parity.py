@@ -24,13 +24,13 @@ from paper_2203_12339_amd.workloads import renderer_for, scene_for  # noqa: E402
 TOL = {"f64": 1e-10, "f32": 1e-5, "bf16": 5e-3, "f16": 5e-3}
 
 
-def _render(w, L=None, th=None, save=False, renderer=None):
+def _render(w, L=None, th=None, save=False, renderer=None, plain=False):
     r = renderer or renderer_for(w)
     L = synth.make_lighting(w) if L is None else L
     th = synth.make_materials(w) if th is None else th
     r.set_lighting(dev_tensor(L, light_dtype(w)))
     r.set_material(dev_tensor(th, "f64"))
-    B = r.render(save=save, force=True)
+    B = r.render(save=save, force=True, plain=plain)
     torch.cuda.synchronize()
     return r, L, th, B.cpu().numpy()
 
@@ -63,6 +63,12 @@ def test_render_matches_oracle(name, kw):
     e = normwise(B, ref)
     say(f"[parity] {name}: normwise {e:.3e} elementwise {elementwise(B, ref):.3e}")
     assert e <= TOL[w.storage], e
+    if w.storage != "f64":
+        # the plain (column, value) row kernel on the same kept sets
+        _, _, _, Bp = _render(w, L, th, renderer=r, plain=True)
+        ep = normwise(Bp, ref)
+        say(f"[parity] {name} rows kernel: normwise {ep:.3e}; tiles vs rows {normwise(B, Bp):.3e}")
+        assert ep <= TOL[w.storage], ep
     r.close()
 
 
