@@ -87,6 +87,10 @@ def main():
                     help="include the adjoint in every step")
     ap.add_argument("--tile", type=int, default=0, help="columns per lane (0 = tuned default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain", action="store_true",
+                    help="use the (column, value) row kernel instead of the tiles")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -123,7 +127,16 @@ def main():
     r.set_material(tt)
     B = torch.empty((w.n_out, w.n_vertices, 3), dtype=ldt, device=dev)
     dB = torch.randn_like(B) if args.backward else None
-    flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0)
+    flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0) | \
+        (tlt.PLAIN_ROWS if args.plain else 0)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe} MiB read + {args.copy_probe} MiB written")
+        del src, dst
     dSH = torch.empty((w.n_light, w.n_sh, 3), dtype=ldt, device=dev)
     dTh = torch.empty((w.n_cfg, 3, 3), dtype=torch.float64, device=dev)
 
@@ -201,6 +214,7 @@ def main():
             "n_vertices": w.n_vertices, "K": w.K, "n_keep": w.n_keep, "n_sh": w.n_sh,
             "storage": w.storage, "lightings": w.n_light, "materials": w.n_cfg,
             "columns": C, "backward": bool(args.backward), "tile": r.tile(),
+            "layout": "rows" if args.plain else "tiles",
             "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),
             "stage_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stage_ms.items()},
         },

@@ -54,6 +54,7 @@ struct tlt_ctx {
   int C = 0, Cs = 0, cpl = 0, n_out = 0, tile_req = 0;
   int buf_nlight = -1, buf_nmat = -1;
   void *Lm = nullptr, *ehat = nullptr, *partial = nullptr, *gcol = nullptr, *V = nullptr;
+  void *ehat2 = nullptr;  // hi|lo split of Ehat for 16-bit tiles
   double *g64 = nullptr, *dg64 = nullptr;
   void *adj = nullptr;
   size_t adj_bytes = 0;
@@ -62,7 +63,7 @@ struct tlt_ctx {
 
   // block-dense tiles (see tlt.h): offsets, union columns, values
   bool tiles = false;
-  int tV = 0, tR = 0, t_blocks = 0;
+  int tV = 0, tR = 0, t_blocks = 0, t_max_union = 0;
   int64_t *t_off = nullptr;
   int32_t *t_ucol = nullptr;
   void *t_val = nullptr;
@@ -129,6 +130,7 @@ int auto_cpl(int C) {
 void free_columns(tlt_ctx *c) {
   dfree(c->Lm);
   dfree(c->ehat);
+  dfree(c->ehat2);
   dfree(c->partial);
   dfree(c->gcol);
   dfree(c->V);
@@ -189,6 +191,9 @@ tlt_status ensure_columns(tlt_ctx *c) {
   tlt_status s;
   if ((s = dalloc(c, &c->Lm, e * c->n_shp * c->Cs, "lighting matrix")) != TLT_OK) return s;
   if ((s = dalloc(c, &c->ehat, e * (size_t)c->n_rows * c->Cs, "Ehat")) != TLT_OK) return s;
+  if (c->tiles && c->vdt != TLT_F32 &&
+      (s = dalloc(c, &c->ehat2, 4 * (size_t)c->n_rows * c->Cs, "Ehat split")) != TLT_OK)
+    return s;
   const int ch_rows = std::min(c->n_rows, 256);
   const int n_chunks = (c->n_rows + ch_rows - 1) / ch_rows;
   if ((s = dalloc(c, &c->partial, e * (size_t)n_chunks * c->Cs, "Haar partials")) != TLT_OK) return s;
@@ -276,12 +281,12 @@ StreamArgs stream_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *
   const char *e = std::getenv("TLT_STREAM_EPL");
   a.epl = e ? std::atoi(e) : 0;
   const char *nt = std::getenv("TLT_STREAM_NT");
-  a.nt = nt ? std::atoi(nt) : 1;
+  a.nt = nt ? std::atoi(nt) : 0;
   return a;
 }
 
-TileArgs tile_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *gcol, void *B,
-                   void *vsave, int vs_stride) {
+TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int C,
+                   const void *gcol, void *B, void *vsave, int vs_stride) {
   TileArgs a;
   std::memset(&a, 0, sizeof(a));
   a.blk_off = c->t_off;
@@ -291,8 +296,10 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *gcol
   a.K = c->K;
   a.R = c->tR;
   a.n_blocks = c->t_blocks;
+  a.max_union = c->t_max_union;
   a.N = c->N;
   a.ehat = ehat;
+  a.ehat2 = ehat2;
   a.Cs = Cs;
   a.C = C;
   a.gcol = gcol;
@@ -300,6 +307,8 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *gcol
   a.B = B;
   a.vsave = vsave;
   a.vs_stride = vs_stride;
+  const char *e = std::getenv("TLT_TILE_KC");
+  a.kc = e ? std::atoi(e) : 0;
   return a;
 }
 
@@ -324,7 +333,7 @@ tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   c->Psh = cplP;
   c->Gs = round_up(cplP, 16);
   const size_t e = c->esz;
-  void *G = nullptr, *part = nullptr, *gz = nullptr;
+  void *G = nullptr, *G2 = nullptr, *part = nullptr, *gz = nullptr;
   tlt_status s;
   Cols ident{c->Psh, 1, 1, 1};
   PrepArgs a = prep_args(c, c->Gs, ident);
@@ -332,16 +341,21 @@ tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   if ((s = dalloc(c, &G, e * (size_t)c->n_rows * c->Gs, "G")) != TLT_OK) goto out;
   if ((s = dalloc(c, &part, e * (size_t)a.n_chunks * c->Gs, "G partials")) != TLT_OK) goto out;
   if ((s = dalloc(c, &gz, e * (size_t)c->K * c->Gs, "zero weights")) != TLT_OK) goto out;
+  if (c->tiles && c->vdt != TLT_F32 &&
+      (s = dalloc(c, &G2, 4 * (size_t)c->n_rows * c->Gs, "G split")) != TLT_OK)
+    goto out;
   {
     a.n_tl_blocks = a.n_chunks * (c->Gs / 16);
     a.sh = nullptr;  // identity lighting: column lm of G is Haar(pad(A o T[:, lm]))
     a.ehat = G;
     a.partial = part;
+    a.ehat2 = G2;
+    a.split = c->vdt == TLT_BF16 ? 1 : 2;
     StreamArgs sa = stream_args(c, G, c->Gs, c->Psh, gz, nullptr, c->P, c->Psh);
     hipError_t he;
     if ((he = hipMemset(gz, 0, e * (size_t)c->K * c->Gs)) != hipSuccess ||
         (he = launch_prep(a, st)) != hipSuccess ||
-        (he = c->tiles ? launch_tiles(tile_args(c, G, c->Gs, c->Psh, nullptr, nullptr, c->P, c->Psh),
+        (he = c->tiles ? launch_tiles(tile_args(c, G, G2, c->Gs, c->Psh, nullptr, nullptr, c->P, c->Psh),
                                       c->vdt, st)
                        : launch_stream(sa, c->vdt, c->fp64, c->Psh, st)) != hipSuccess ||
         (he = hipStreamSynchronize(st)) != hipSuccess) {
@@ -353,6 +367,7 @@ tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   s = TLT_OK;
 out:
   dfree(G);
+  dfree(G2);
   dfree(part);
   dfree(gz);
   return s;
@@ -652,6 +667,8 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
       c->tV = tV;
       c->tR = tV * c->K;
       c->t_blocks = (int)tb.n_blocks;
+      for (int64_t bb = 0; bb < tb.n_blocks; ++bb)
+        c->t_max_union = std::max<int>(c->t_max_union, (int)(tb.blk_off[bb + 1] - tb.blk_off[bb]));
       const size_t nu = tb.ucol.size();
       const size_t nvals = nu * (size_t)c->tR;
       c->t_val_bytes = nvals * (c->vdt == TLT_F32 ? 4 : 2);
@@ -758,6 +775,8 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     a.sh = c->sh;
     a.ehat = c->ehat;
     a.partial = c->partial;
+    a.ehat2 = c->ehat2;
+    a.split = c->vdt == TLT_BF16 ? 1 : 2;
     if (c->n_zero > 0 && !use_tiles) {
       a.B = B;
       a.zero_v = c->zero_v;
@@ -771,7 +790,8 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     {
       StageTimer t(c, 2, st);
       if (use_tiles) {
-        HIPC(c, launch_tiles(tile_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs),
+        HIPC(c, launch_tiles(tile_args(c, c->ehat, c->ehat2, c->Cs, c->C, c->gcol, B,
+                                       save ? c->V : nullptr, c->Cs),
                              c->vdt, st));
       } else {
         StreamArgs sa = stream_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs);

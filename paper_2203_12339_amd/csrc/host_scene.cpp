@@ -318,16 +318,15 @@ extern "C" tlt_status tlt_prepare_scene(tlt_scene *s) {
 
 namespace tlt {
 
-static inline double interp_basis(const double *rn, const double *bk, int nr, double r) {
-  if (r >= rn[nr - 1]) return bk[nr - 1];
-  if (r <= 0.0) return bk[0];
+static inline int node_of(const double *rn, int nr, double r) {
+  if (r >= rn[nr - 1]) return nr - 1;  // at or beyond the last node
+  if (r <= 0.0) return 0;
   int n = (int)((nr - 1) * std::sqrt(r / rn[nr - 1]));
   if (n > nr - 2) n = nr - 2;
   if (n < 0) n = 0;
   while (n > 0 && r < rn[n]) --n;
   while (n < nr - 2 && r >= rn[n + 1]) ++n;
-  const double slope = (bk[n + 1] - bk[n]) / (rn[n + 1] - rn[n]);
-  return slope * (r - rn[n]) + bk[n];
+  return n;
 }
 
 static void haar_inplace(double *x, double *tmp, int64_t n) {
@@ -343,25 +342,45 @@ static void haar_inplace(double *x, double *tmp, int64_t n) {
   }
 }
 
+static inline uint64_t mag_key(double v) {
+  uint64_t u;
+  std::memcpy(&u, &v, 8);
+  return u & 0x7fffffffffffffffull;  // |v| as an ordered integer
+}
+
 // Keeps the n_keep entries of largest |x| (ties to the lower index);
-// writes their indices ascending and their values.
-static void select_top(const double *x, int64_t n, int64_t n_keep, std::vector<double> &mag,
-                       int32_t *col, double *val) {
+// writes their indices ascending and their values.  The threshold is found
+// from a histogram of the top 12 bits of |x| (ordered as integers), then an
+// exact selection among the entries of the boundary bucket.
+static void select_top(const double *x, int64_t n, int64_t n_keep, std::vector<uint64_t> &cand,
+                       std::vector<uint32_t> &hist, int32_t *col, double *val) {
   if (n_keep >= n) {
     for (int64_t j = 0; j < n; ++j) { col[j] = (int32_t)j; val[j] = x[j]; }
     return;
   }
-  mag.resize(n);
-  for (int64_t j = 0; j < n; ++j) mag[j] = std::fabs(x[j]);
-  std::nth_element(mag.begin(), mag.begin() + (n - n_keep), mag.end());
-  const double thr = mag[n - n_keep];
-  int64_t gt = 0;
-  for (int64_t j = 0; j < n; ++j) gt += std::fabs(x[j]) > thr;
+  hist.assign(4096, 0);
+  for (int64_t j = 0; j < n; ++j) hist[mag_key(x[j]) >> 51]++;
+  int64_t above = 0;
+  int bucket = 4095;
+  for (; bucket >= 0; --bucket) {
+    if (above + hist[bucket] >= n_keep) break;
+    above += hist[bucket];
+  }
+  cand.clear();
+  for (int64_t j = 0; j < n; ++j) {
+    const uint64_t k = mag_key(x[j]);
+    if ((int)(k >> 51) == bucket) cand.push_back(k);
+  }
+  const int64_t need = n_keep - above;  // 1 <= need <= cand.size()
+  std::nth_element(cand.begin(), cand.begin() + (cand.size() - need), cand.end());
+  const uint64_t thr = cand[cand.size() - need];
+  int64_t gt = above;
+  for (uint64_t k : cand) gt += k > thr;
   int64_t ties = n_keep - gt, w = 0;
   for (int64_t j = 0; j < n; ++j) {
-    const double a = std::fabs(x[j]);
-    bool take = a > thr;
-    if (!take && a == thr && ties > 0) {
+    const uint64_t k = mag_key(x[j]);
+    bool take = k > thr;
+    if (!take && k == thr && ties > 0) {
       take = true;
       --ties;
     }
@@ -376,10 +395,19 @@ static void select_top(const double *x, int64_t n, int64_t n_keep, std::vector<d
 void host_build_rows(int n_rows, int n_cols, int K, int nr, int wavelet, int64_t n_keep,
                      const double *row_pos, const double *rn, const double *basis,
                      int32_t *col, double *val, int n_threads, int N, const double *pos) {
+  // per-node slopes of every basis function, as in linear interpolation
+  std::vector<double> slope((size_t)K * nr, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int m = 0; m + 1 < nr; ++m)
+      slope[(size_t)k * nr + m] =
+          (basis[(size_t)k * nr + m + 1] - basis[(size_t)k * nr + m]) / (rn[m + 1] - rn[m]);
   std::atomic<int64_t> next(0);
   const int64_t block = 16;
   auto worker = [&]() {
-    std::vector<double> r(N), x(n_cols), tmp(n_cols), mag;
+    std::vector<double> dr(N), x(n_cols), tmp(n_cols);
+    std::vector<int32_t> node(N);
+    std::vector<uint64_t> cand;
+    std::vector<uint32_t> hist;
     for (;;) {
       const int64_t o0 = next.fetch_add(block);
       if (o0 >= n_rows) break;
@@ -390,15 +418,22 @@ void host_build_rows(int n_rows, int n_cols, int K, int nr, int wavelet, int64_t
           const double dx = xo[0] - pos[3 * (size_t)i];
           const double dy = xo[1] - pos[3 * (size_t)i + 1];
           const double dz = xo[2] - pos[3 * (size_t)i + 2];
-          r[i] = std::sqrt(dx * dx + dy * dy + dz * dz);
+          const double r = std::sqrt(dx * dx + dy * dy + dz * dz);
+          const int m = node_of(rn, nr, r);
+          node[i] = m;
+          dr[i] = r - rn[m];
         }
         for (int k = 0; k < K; ++k) {
           const double *bk = &basis[(size_t)k * nr];
-          for (int i = 0; i < N; ++i) x[i] = interp_basis(rn, bk, nr, r[i]);
+          const double *sk = &slope[(size_t)k * nr];
+          for (int i = 0; i < N; ++i) {
+            const int m = node[i];
+            x[i] = (m == nr - 1) ? bk[nr - 1] : sk[m] * dr[i] + bk[m];
+          }
           for (int i = N; i < n_cols; ++i) x[i] = 0.0;
           if (wavelet == TLT_WAVELET_HAAR) haar_inplace(x.data(), tmp.data(), n_cols);
           const size_t rowoff = (size_t)(o * K + k) * (size_t)n_keep;
-          select_top(x.data(), n_cols, n_keep, mag, col + rowoff, val + rowoff);
+          select_top(x.data(), n_cols, n_keep, cand, hist, col + rowoff, val + rowoff);
         }
       }
     }

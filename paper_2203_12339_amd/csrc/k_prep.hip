@@ -153,6 +153,28 @@ template <> struct MfmaOut<double> {
 constexpr int TL_CH = 256;
 constexpr int TL_STRIDE = 17;
 
+// Irradiance store: float Ehat and, for 16-bit transport tiles, its split
+// into a high 16-bit part and the 16-bit rounding of the remainder, packed
+// as (hi | lo << 16), so the tile kernel gathers one word per element.
+__device__ __forceinline__ uint32_t split16(float x, int kind) {
+  if (kind == 1) {
+    const __bf16 hi = (__bf16)x;
+    const __bf16 lo = (__bf16)(x - (float)hi);
+    return (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+  }
+  const _Float16 hi = (_Float16)x;
+  const _Float16 lo = (_Float16)(x - (float)hi);
+  return (uint32_t)__builtin_bit_cast(uint16_t, hi) | ((uint32_t)__builtin_bit_cast(uint16_t, lo) << 16);
+}
+
+template <typename CT>
+__device__ __forceinline__ void store_e(CT *ehat, uint32_t *ehat2, int split, size_t idx, CT v) {
+  ehat[idx] = v;
+  if constexpr (sizeof(CT) == 4) {
+    if (ehat2 != nullptr) ehat2[idx] = split16(v, split);
+  }
+}
+
 template <typename TT, typename CT>
 __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   typedef typename MfmaOut<CT>::V4 V4;
@@ -167,6 +189,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   const CT *sh = (const CT *)a.sh;
   const CT *area = (const CT *)a.area;
   CT *ehat = (CT *)a.ehat;
+  uint32_t *ehat2 = (uint32_t *)a.ehat2;
   CT *partial = (CT *)a.partial;
 
   // lighting column of this lane (B operand column n = li)
@@ -216,7 +239,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
     for (int idx = threadIdx.x; idx < a.ch_rows * 16; idx += 256) {
       const int lr = idx >> 4, cc = idx & 15;
       const int r = i0 + lr;
-      if (r < a.n_rows) ehat[(size_t)r * a.Cs + c0 + cc] = x[lr * TL_STRIDE + cc];
+      if (r < a.n_rows) store_e(ehat, ehat2, a.split, (size_t)r * a.Cs + c0 + cc, x[lr * TL_STRIDE + cc]);
     }
     return;
   }
@@ -233,7 +256,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
         const CT p = x[(2 * i) * TL_STRIDE + cc];
         const CT q = x[(2 * i + 1) * TL_STRIDE + cc];
         const int64_t j = (int64_t)half * (a.n_chunks + chunk) + i;
-        ehat[j * a.Cs + c0 + cc] = (p - q) * h;
+        store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (p - q) * h);
         sv[u] = (p + q) * h;
       }
     }
@@ -246,7 +269,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
     __syncthreads();
   }
   if (a.n_chunks == 1) {
-    if (threadIdx.x < 16) ehat[c0 + threadIdx.x] = x[threadIdx.x];
+    if (threadIdx.x < 16) store_e(ehat, ehat2, a.split, (size_t)c0 + threadIdx.x, x[threadIdx.x]);
     return;
   }
   if (threadIdx.x < 16) partial[(size_t)chunk * a.Cs + c0 + threadIdx.x] = x[threadIdx.x];
@@ -257,7 +280,8 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
 // is the cheap way to make them visible).  grid: Cs workgroups.
 template <typename CT>
 __global__ __launch_bounds__(256) void k_haar_top(const CT *__restrict__ partial, int n_chunks,
-                                                  int Cs, CT *__restrict__ ehat) {
+                                                  int Cs, CT *__restrict__ ehat,
+                                                  uint32_t *__restrict__ ehat2, int split) {
   extern __shared__ __align__(16) unsigned char raw[];
   CT *s0 = reinterpret_cast<CT *>(raw);
   CT *s1 = s0 + n_chunks;
@@ -270,7 +294,7 @@ __global__ __launch_bounds__(256) void k_haar_top(const CT *__restrict__ partial
     const int half = len >> 1;
     for (int i = threadIdx.x; i < half; i += 256) {
       const CT p = src[2 * i], q = src[2 * i + 1];
-      ehat[(size_t)(half + i) * Cs + c] = (p - q) * h;
+      store_e(ehat, ehat2, split, (size_t)(half + i) * Cs + c, (p - q) * h);
       dst[i] = (p + q) * h;
     }
     __syncthreads();
@@ -278,7 +302,7 @@ __global__ __launch_bounds__(256) void k_haar_top(const CT *__restrict__ partial
     src = dst;
     dst = t;
   }
-  if (threadIdx.x == 0) ehat[c] = src[0];
+  if (threadIdx.x == 0) store_e(ehat, ehat2, split, (size_t)c, src[0]);
 }
 
 template <typename CT>
@@ -337,10 +361,12 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t st) {
     const size_t lds2 = (size_t)a.n_chunks * 3 / 2 * (a.fp64 ? 8 : 4);
     if (a.fp64)
       hipLaunchKernelGGL((k_haar_top<double>), dim3(a.Cs), dim3(256), lds2, st,
-                         (const double *)a.partial, a.n_chunks, a.Cs, (double *)a.ehat);
+                         (const double *)a.partial, a.n_chunks, a.Cs, (double *)a.ehat,
+                         (uint32_t *)nullptr, 0);
     else
       hipLaunchKernelGGL((k_haar_top<float>), dim3(a.Cs), dim3(256), lds2, st,
-                         (const float *)a.partial, a.n_chunks, a.Cs, (float *)a.ehat);
+                         (const float *)a.partial, a.n_chunks, a.Cs, (float *)a.ehat,
+                         (uint32_t *)a.ehat2, a.split);
     e = hipGetLastError();
   }
   return e;

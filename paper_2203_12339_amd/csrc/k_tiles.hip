@@ -23,6 +23,8 @@
 // Operand layout (measured on gfx950): lane l supplies A[l%16][kpl*(l/16)+i]
 // and B[kpl*(l/16)+i][l%16], i < kpl; result v of lane l is D[4*(l/16)+v][l%16].
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace tlt {
@@ -80,94 +82,125 @@ template <> struct TileKind<2> {
 };
 
 // Work split: a workgroup owns one block and one group of NT <= 3 16-column
-// tiles (wider launches run as several column groups; they re-read the same
-// W block, which the XCD's L2 serves).  Its WM = MT/MTW waves each compute
-// MTW m-tiles x NT n-tiles.  Per chunk of KC k-steps the gathered
-// irradiance is staged once in LDS (B-operand fragment order) and read by
-// every wave; each wave loads the W fragments of its own m-tiles for the
-// NEXT chunk while it multiplies the current one, so the HBM latency hides
-// behind a whole chunk of matrix work.
-constexpr int TILE_IPT = 4;          // staged items per thread and chunk
-constexpr int TILE_LDS = 32 * 1024;  // staging budget per workgroup
+// tiles (wider launches run as several column groups).  Its WM = MT/MTW
+// waves each compute MTW m-tiles x NT n-tiles.  The gathered irradiance of
+// up to `chunk` union entries is staged in LDS (B-operand fragment order) in
+// one pass and read by every wave -- for narrow launches the whole union of
+// a block fits one chunk, so the block synchronises once.  W streams through
+// a PD-deep register ring per wave (fragments PD steps ahead of use), which
+// runs across chunk boundaries, so HBM latency hides behind PD steps of
+// matrix work regardless of the staging.
+constexpr int TILE_LDS = 64 * 1024;  // staging budget per workgroup
 
-template <int KIND, int MTW, int NT, int KCMAX>
+template <int KIND, int MTW, int NT, int PD, int IPT>
 __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   typedef TileKind<KIND> TK;
   typedef typename TK::BElem BElem;
   typedef typename TK::BFrag BFrag;
   typedef typename TK::AFrag AFrag;
   constexpr int KS = TK::KSTEP, KPL = TK::KPL, H = TK::H;
-  constexpr int FRAG = 64 * KPL;  // elements per fragment
   extern __shared__ __align__(16) unsigned char smem[];
   BElem *stage = reinterpret_cast<BElem *>(smem);
 
-  const int b = xcd_remap(blockIdx.x, a.n_blocks);
-  if (b >= a.n_blocks) return;
+  // Workgroup h runs on XCD h % 8.  Each XCD takes a contiguous range of
+  // blocks, and the column groups of one block occupy consecutive slots of
+  // the same XCD, so they run together and share the W block through L2.
+  const int ng = a.n_groups;
+  const int per_xcd = (a.n_blocks + 7) / 8;
+  const int slot = blockIdx.x >> 3;
+  const int b = (blockIdx.x & 7) * per_xcd + slot / ng;
+  const int grp = slot % ng;
+  if (slot / ng >= per_xcd || b >= a.n_blocks) return;
   const int MT = a.R / 16;
-  const int WN = a.wn;
-  const int NTB = WN * NT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = wave / WN, wn = wave % WN;
+  const int wm = wave;  // waves split the m-tiles
   const int nthr = blockDim.x;
-  const int cbase = blockIdx.y * NTB * 16;  // first column of the block's group
-  const int KC = a.kc;                      // k-steps per staged chunk
+  const int cbase = grp * NT * 16;
+  const int cg = min(NT * 16, a.C - cbase);  // real columns of this group
   const int64_t u0 = a.blk_off[b];
   const int n_steps = (int)((a.blk_off[b + 1] - u0) / KS);
-  const int n_chunks = (n_steps + KC - 1) / KC;
+  const int CS = a.kc;  // k-steps per staged chunk (a multiple of PD)
   const int32_t *__restrict__ ucol = a.ucol + u0;
   const float *__restrict__ ehat = (const float *)a.ehat;
-  const int64_t vbase = u0 * a.R;  // first value element of this block
-  const int items = KC * 4 * NTB * 16;
+  const int64_t vbase = u0 * a.R;
 
-  // staging item = (step sl, lane group lg, column n): KPL consecutive union
-  // entries of one column -> one 16-byte (or 4-byte) LDS store.
-  float gat[TILE_IPT][KPL];
-  auto gather = [&](int chunk) {
+  // Staging.  The union column ids of the whole block are read into LDS
+  // once.  float32: item = (step sl, lane group lg, real column n), one
+  // 4-byte gather and store.  16-bit kinds: item = (step, lane group, column
+  // quad), eight 16-byte gathers of (hi|lo) words -- 4 columns of KPL = 8
+  // consecutive union entries -- unpacked into 2 x 4 fragment stores.  A
+  // thread's item decomposition is the same for every chunk.  The gathers
+  // of the next chunk are issued into registers before the current chunk's
+  // matrix work and stored to LDS after it.
+  int *uc = reinterpret_cast<int *>(smem + a.uc_offset);
+  for (int i = threadIdx.x; i < n_steps * KS; i += nthr) uc[i] = ucol[i];
+  constexpr int QW = KIND == 0 ? 1 : 4;  // columns per item
+  const int cq = (cg + QW - 1) / QW;     // items per (step, lane group)
+  int it_sl[IPT], it_eoff[IPT], it_col[IPT], it_lds[IPT];
 #pragma unroll
-    for (int it = 0; it < TILE_IPT; ++it) {
-      const int item = threadIdx.x + it * nthr;
-      const int n = item % (NTB * 16);
-      const int lg = (item / (NTB * 16)) % 4;
-      const int sl = item / (NTB * 16 * 4);
-      const int s = chunk * KC + sl;
-      const int c = cbase + n;
-      const bool ok = item < items && s < n_steps && c < a.Cs;
+  for (int it = 0; it < IPT; ++it) {
+    const int item = threadIdx.x + it * nthr;
+    const int q = item % cq;
+    const int lg = (item / cq) % 4;
+    const int sl = item / (cq * 4);
+    const int n = q * QW;
+    it_sl[it] = sl;
+    it_eoff[it] = sl * KS + KPL * lg;
+    it_col[it] = cbase + n;
+    if constexpr (KIND == 0)
+      it_lds[it] = (sl * 4 + lg) * cg + n;
+    else
+      it_lds[it] = ((sl * NT + n / 16) * H * 64 + lg * 16 + (n % 16)) * KPL;
+  }
+  __syncthreads();  // union ids visible
+  typedef typename std::conditional<KIND == 0, float, uint4>::type GT;
+  const GT *__restrict__ esrc = (const GT *)(KIND == 0 ? a.ehat : a.ehat2);
+  GT g[IPT][KPL];
+  auto gather = [&](int s0, int ns) {
+#pragma unroll
+    for (int it = 0; it < IPT; ++it) {
+      const bool ok = it_sl[it] < ns;
 #pragma unroll
       for (int i = 0; i < KPL; ++i) {
-        const int j = ok ? ucol[s * KS + KPL * lg + i] : 0;
-        const float x = ehat[(int64_t)j * a.Cs + (ok ? c : 0)];
-        gat[it][i] = ok ? x : 0.f;
+        const int j = ok ? uc[s0 * KS + it_eoff[it] + i] : 0;
+        const int64_t idx = (int64_t)j * a.Cs + (ok ? it_col[it] : 0);
+        if constexpr (KIND == 0)
+          g[it][i] = esrc[idx];
+        else
+          g[it][i] = *(const uint4 *)((const uint32_t *)esrc + idx);
       }
     }
   };
-  auto stage_write = [&]() {
+  auto stage_write = [&](int ns) {
 #pragma unroll
-    for (int it = 0; it < TILE_IPT; ++it) {
-      const int item = threadIdx.x + it * nthr;
-      if (item < items) {
-        const int n = item % (NTB * 16);
-        const int lg = (item / (NTB * 16)) % 4;
-        const int sl = item / (NTB * 16 * 4);
-        const int nt = n / 16, ln = lg * 16 + (n % 16);
-        BFrag hi, lo;
+    for (int it = 0; it < IPT; ++it) {
+      if (it_sl[it] < ns) {
+        if constexpr (KIND == 0) {
+          stage[it_lds[it]] = g[it][0];
+        } else {
 #pragma unroll
-        for (int i = 0; i < KPL; ++i) {
-          BElem h_, l_;
-          TK::split(gat[it][i], h_, l_);
-          if constexpr (KPL == 1) {
-            hi = h_;
-            lo = l_;
-          } else {
-            hi[i] = h_;
-            lo[i] = l_;
+          for (int jj = 0; jj < 4; ++jj) {
+            uint32_t hw[KPL / 2], lw[KPL / 2];
+#pragma unroll
+            for (int i = 0; i < KPL / 2; ++i) {
+              const uint32_t w0 = g[it][2 * i][jj], w1 = g[it][2 * i + 1][jj];
+              hw[i] = __builtin_amdgcn_perm(w1, w0, 0x05040100u);
+              lw[i] = __builtin_amdgcn_perm(w1, w0, 0x07060302u);
+            }
+            *reinterpret_cast<BFrag *>(stage + it_lds[it] + jj * KPL) = __builtin_bit_cast(BFrag, hw);
+            *reinterpret_cast<BFrag *>(stage + it_lds[it] + jj * KPL + 64 * KPL) =
+                __builtin_bit_cast(BFrag, lw);
           }
         }
-        *reinterpret_cast<BFrag *>(stage + ((size_t)((sl * NTB + nt) * H + 0) * 64 + ln) * KPL) = hi;
-        if constexpr (H == 2)
-          *reinterpret_cast<BFrag *>(stage + ((size_t)((sl * NTB + nt) * H + 1) * 64 + ln) * KPL) = lo;
       }
     }
   };
+  // 16-bit kinds: padded columns of the group read zeros, clear the buffer
+  if (KIND != 0 && cg < NT * 16) {
+    const int words = CS * NT * H * 64 * KPL * (int)sizeof(BElem) / 4;
+    for (int i = threadIdx.x; i < words; i += nthr) reinterpret_cast<uint32_t *>(smem)[i] = 0u;
+    __syncthreads();
+  }
 
   f32x4 acc[MTW][NT];
 #pragma unroll
@@ -175,56 +208,58 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
 
-  // W fragments of a whole chunk, for this wave's m-tiles (clamped loads
-  // past the last step are never used)
-  auto load_a = [&](int chunk, AFrag (&dst)[KCMAX][MTW]) {
+  // W fragments for step s of this wave's m-tiles (clamped past the end)
+  auto load_a = [&](int s, AFrag (&dst)[MTW]) {
+    const int ss = min(s, n_steps - 1);
 #pragma unroll
-    for (int sl = 0; sl < KCMAX; ++sl) {
-      const int ss = min(chunk * KC + min(sl, KC - 1), n_steps - 1);
-#pragma unroll
-      for (int m = 0; m < MTW; ++m) {
-        const int t = wm * MTW + m;
-        dst[sl][m] = TK::load_a(a.val, vbase + ((int64_t)(ss * MT + t) * 64 + lane) * KPL);
-      }
+    for (int m = 0; m < MTW; ++m) {
+      const int t = wm * MTW + m;
+      dst[m] = TK::load_a(a.val, vbase + ((int64_t)(ss * MT + t) * 64 + lane) * KPL);
     }
   };
+  AFrag ring[PD][MTW];
+#pragma unroll
+  for (int p = 0; p < PD; ++p) load_a(p, ring[p]);
 
-  AFrag acur[KCMAX][MTW], anext[KCMAX][MTW];
-  gather(0);
-  load_a(0, acur);
-  stage_write();
+  int ns = min(CS, n_steps);
+  gather(0, ns);
+  stage_write(ns);
   __syncthreads();
-  for (int ch = 0; ch < n_chunks; ++ch) {
-    const bool more = ch + 1 < n_chunks;
-    if (more) {
-      gather(ch + 1);
-      load_a(ch + 1, anext);
-    }
-    const int steps_here = min(KC, n_steps - ch * KC);
+  for (int s0 = 0; s0 < n_steps; s0 += CS) {
+    const int nxt = s0 + CS;
+    const int ns_next = min(CS, n_steps - nxt);
+    if (ns_next > 0) gather(nxt, ns_next);
+    for (int g0 = 0; g0 < ns; g0 += PD) {
 #pragma unroll
-    for (int sl = 0; sl < KCMAX; ++sl) {
-      if (sl < steps_here) {
+      for (int p = 0; p < PD; ++p) {
+        const int sl = g0 + p;
+        if (sl < ns) {
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
+          for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-          for (int h = 0; h < H; ++h) {
-            const BFrag bf = *reinterpret_cast<const BFrag *>(
-                stage + ((size_t)((sl * NTB + wn * NT + nt) * H + h) * 64 + lane) * KPL);
+            for (int h = 0; h < H; ++h) {
+              BFrag bf;
+              if constexpr (KIND == 0) {
+                const int n = nt * 16 + (lane & 15);
+                bf = (n < cg) ? stage[((size_t)sl * 4 + (lane >> 4)) * cg + n] : 0.f;
+              } else {
+                bf = *reinterpret_cast<const BFrag *>(
+                    stage + ((size_t)((sl * NT + nt) * H + h) * 64 + lane) * KPL);
+              }
 #pragma unroll
-            for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(acur[sl][m], bf, acc[m][nt]);
+              for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf, acc[m][nt]);
+            }
           }
+          load_a(s0 + sl + PD, ring[p]);  // refill this slot PD steps ahead
         }
       }
     }
-    __syncthreads();
-    if (more) {
-      stage_write();
+    if (ns_next > 0) {
+      __syncthreads();  // every wave is done with this chunk
+      stage_write(ns_next);
       __syncthreads();
-#pragma unroll
-      for (int sl = 0; sl < KCMAX; ++sl)
-#pragma unroll
-        for (int m = 0; m < MTW; ++m) acur[sl][m] = anext[sl][m];
     }
+    ns = ns_next;
   }
 
   // ---- epilogue: v_k (optional) and the K-term fusion into B ----
@@ -233,13 +268,12 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   const float *gcol = (const float *)a.gcol;
   float *vsave = (float *)a.vsave;
   float *B = (float *)a.B;
-  const int wcol = cbase + wn * NT * 16;  // first column of this wave
   if (vsave != nullptr) {
 #pragma unroll
     for (int m = 0; m < MTW; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int c = wcol + nt * 16 + ln;
+        const int c = cbase + nt * 16 + ln;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = (wm * MTW + m) * 16 + 4 * lg + v;
@@ -255,7 +289,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     for (int m = 0; m < MTW; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int c = wcol + nt * 16 + ln;
+        const int c = cbase + nt * 16 + ln;
         float sum = 0.f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -274,13 +308,14 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       }
   } else {
     // generic K: weighted rows through LDS, then sums over the K rows
-    float *out = reinterpret_cast<float *>(smem);  // [R][NTB*16]
-    const int CW = NTB * 16;
+    __syncthreads();
+    float *out = reinterpret_cast<float *>(smem);  // [R][NT*16]
+    constexpr int CW = NT * 16;
 #pragma unroll
     for (int m = 0; m < MTW; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
-        const int cl = wn * NT * 16 + nt * 16 + ln;
+        const int cl = nt * 16 + ln;
         const int c = cbase + cl;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -304,48 +339,57 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   }
 }
 
-template <int KIND, int MTW, int NT, int KCMAX>
+template <int KIND, int MTW, int NT, int PD, int IPT>
 static hipError_t tiles_go(TileArgs a, int nt_total, hipStream_t st) {
   typedef TileKind<KIND> TK;
   const int MT = a.R / 16;
   if (MT % MTW) return hipErrorInvalidValue;
-  const int WM = MT / MTW;
+  const int threads = (MT / MTW) * 64;
+  const int cmax = std::min(a.C, NT * 16);  // real columns of the widest group
+  const int qw = KIND == 0 ? 1 : 4;
+  const int items_per_step = 4 * ((cmax + qw - 1) / qw);
+  const size_t per_step = KIND == 0 ? (size_t)4 * cmax * sizeof(float)
+                                    : (size_t)NT * TK::H * 64 * TK::KPL * sizeof(typename TK::BElem);
+  int cs = std::min<int>((int)(TILE_LDS / per_step), IPT * threads / items_per_step);
+  if (a.kc > 0) cs = std::min(cs, a.kc);  // caller override (tuning)
+  cs = std::max(PD, cs / PD * PD);
+  if ((size_t)cs * items_per_step > (size_t)IPT * threads) return hipErrorInvalidValue;
+  a.kc = cs;
   a.wn = 1;
-  const int threads = WM * 64;
-  const size_t per_step = (size_t)NT * TK::H * 64 * TK::KPL * sizeof(typename TK::BElem);
-  int kc = (int)std::min<size_t>(TILE_LDS / per_step, (size_t)TILE_IPT * threads / (64 * NT));
-  kc = std::max(1, std::min(kc, KCMAX));
-  a.kc = kc;
   const bool reg_epi = a.K == 4 || a.K == 8 || a.K == 16;
-  const size_t lds = std::max((size_t)kc * per_step,
-                              reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
-  const int ngroups = (nt_total + NT - 1) / NT;
-  const int hw = ((a.n_blocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_tiles<KIND, MTW, NT, KCMAX>), dim3(hw, ngroups), dim3(threads), lds, st, a);
+  size_t stage = std::max((size_t)cs * per_step,
+                          reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
+  stage = (stage + 15) / 16 * 16;
+  a.uc_offset = (int)stage;
+  const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  a.n_groups = (nt_total + NT - 1) / NT;
+  const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
+  hipLaunchKernelGGL((k_tiles<KIND, MTW, NT, PD, IPT>), dim3(hw), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
-// Shapes: float32 tiles keep one m-tile per wave and stage up to 16 short
-// k-steps per chunk; 16-bit tiles give each wave two (or three) m-tiles and
-// stage up to 4 k-steps of 32 entries.
+// Shapes: float32 tiles keep one m-tile per wave, one 16-column tile per
+// group, a 16-step W ring and 8 staged items per thread (a narrow union fits
+// one chunk); 16-bit tiles use up to three 16-column tiles per group, a
+// 4-step ring, one gathered item (4 columns x 8 entries) per thread and
+// chunk, and two m-tiles per wave when a block has eight.
 template <int KIND>
 static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
   const int nt = (a.C + 15) / 16;
   const int MT = a.R / 16;
   const int ntw = nt < 3 ? nt : 3;
   if constexpr (KIND == 0) {
-    if (ntw == 1) return tiles_go<KIND, 1, 1, 16>(a, nt, st);
-    if (ntw == 2) return tiles_go<KIND, 1, 2, 16>(a, nt, st);
-    return tiles_go<KIND, 1, 3, 16>(a, nt, st);
+    return tiles_go<KIND, 1, 1, 16, 8>(a, nt, st);
   } else {
-  if (MT == 6) {
-    if (ntw == 1) return tiles_go<KIND, 3, 1, 4>(a, nt, st);
-    if (ntw == 2) return tiles_go<KIND, 3, 2, 4>(a, nt, st);
-    return tiles_go<KIND, 3, 3, 4>(a, nt, st);
-  }
-  if (ntw == 1) return tiles_go<KIND, 2, 1, 4>(a, nt, st);
-  if (ntw == 2) return tiles_go<KIND, 2, 2, 4>(a, nt, st);
-  return tiles_go<KIND, 2, 3, 4>(a, nt, st);
+    if (MT == 8) {
+      if (ntw == 1) return tiles_go<KIND, 2, 1, 4, 1>(a, nt, st);
+      if (ntw == 2) return tiles_go<KIND, 2, 2, 4, 1>(a, nt, st);
+      return tiles_go<KIND, 2, 3, 4, 1>(a, nt, st);
+    }
+    if (ntw == 1) return tiles_go<KIND, 1, 1, 4, 1>(a, nt, st);
+    if (ntw == 2) return tiles_go<KIND, 1, 2, 4, 1>(a, nt, st);
+    return tiles_go<KIND, 1, 3, 4, 1>(a, nt, st);
   }
 }
 

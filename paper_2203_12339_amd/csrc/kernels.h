@@ -45,6 +45,8 @@ struct PrepArgs {
   int haar, ch_rows, n_rows, n_chunks;
   void *ehat;              // [n_rows][Cs]
   void *partial;           // [n_chunks][Cs]
+  void *ehat2;             // [n_rows][Cs] hi|lo 16-bit split of Ehat, or nullptr
+  int split;               // 1 = bf16 hi/lo, 2 = f16 hi/lo
   // clearing of B at split vertices
   int n_zero_blocks;
   void *B;                 // [n_out][N][3]
@@ -83,13 +85,15 @@ struct TileArgs {
   const void *val;         // fragment-ordered values
   int V, K, R, n_blocks, N;
   const void *ehat;        // [n_rows][Cs] float32
+  const void *ehat2;       // [n_rows][Cs] hi|lo split (16-bit kinds)
   int Cs, C;
   const void *gcol;        // [K][Cs] float32, or nullptr with B == nullptr
   const int32_t *perm;
   void *B;                 // [n_out][N][3] float32 or nullptr
   void *vsave;             // [K][N][vs_stride] or nullptr
   int vs_stride;
-  int wn, kc;              // set by launch_tiles: waves along columns, k-steps per chunk
+  int max_union;           // largest union of a block (entries)
+  int wn, kc, n_groups, uc_offset;  // set by launch_tiles
 };
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
