@@ -9,7 +9,8 @@ original vertex order -- every stage recomputed (TLT_FORCE_FULL).  With
 before timing starts.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-  python bench.py [--config c2|c4|c5] [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--config haar-f32-10242|batch64-bf16-40962|large-f16-163842]
+                  [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
 
@@ -82,7 +83,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--config", default="haar-f32-10242",
+                    choices=["haar-f32-10242", "batch64-bf16-40962", "large-f16-163842"])
     ap.add_argument("--backward", action="store_true",
                     help="include the adjoint in every step")
     ap.add_argument("--tile", type=int, default=0, help="columns per lane (0 = tuned default)")

@@ -85,23 +85,23 @@ SIGMA_S_RANGE = (0.5, 3.0)        # 1/mm (reduced scattering sigma_s')
 ETA_DEFAULT = 1.3
 
 WORKLOADS = {
-    "c1": Workload("c1", subdiv=3, radius=10.0, noise=0.02, n_sh=16, K=4,
+    "dense-f64-642": Workload("dense-f64-642", subdiv=3, radius=10.0, noise=0.02, n_sh=16, K=4,
                    keep=None, storage="f64", wavelet="none", n_light=1,
                    n_cfg=1, seed=1,
                    description="plain method, FP64, dense transport, N=642"),
-    "c2": Workload("c2", subdiv=5, radius=10.0, noise=0.02, n_sh=25, K=6,
+    "haar-f32-10242": Workload("haar-f32-10242", subdiv=5, radius=10.0, noise=0.02, n_sh=25, K=6,
                    keep=0.05, storage="f32", wavelet="haar", n_light=1,
                    n_cfg=1, seed=2,
                    description="FP32 wavelet-sparse, N=10242, 5% kept"),
-    "c3": Workload("c3", subdiv=3, radius=10.0, noise=0.02, n_sh=25, K=4,
+    "grad-f64-642": Workload("grad-f64-642", subdiv=3, radius=10.0, noise=0.02, n_sh=25, K=4,
                    keep=None, storage="f64", wavelet="none", n_light=1,
                    n_cfg=1, seed=3,
                    description="differentiable, N=642, 75 SH coefficients"),
-    "c4": Workload("c4", subdiv=6, radius=10.0, noise=0.02, n_sh=25, K=8,
+    "batch64-bf16-40962": Workload("batch64-bf16-40962", subdiv=6, radius=10.0, noise=0.02, n_sh=25, K=8,
                    keep=0.02, storage="bf16", wavelet="haar", n_light=64,
                    n_cfg=64, seed=4,
                    description="batched BF16, N=40962, 2% kept, 64 pairs"),
-    "c5": Workload("c5", subdiv=7, radius=10.0, noise=0.02, n_sh=36, K=8,
+    "large-f16-163842": Workload("large-f16-163842", subdiv=7, radius=10.0, noise=0.02, n_sh=36, K=8,
                    keep=0.01, storage="f16", wavelet="haar", n_light=16,
                    n_cfg=1, seed=5, sample_rows=2048,
                    description="large FP16, N=163842, 1% kept, 16 lights"),

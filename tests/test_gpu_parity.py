@@ -36,21 +36,21 @@ def _render(w, L=None, th=None, save=False, renderer=None, plain=False):
 
 
 CASES = [
-    ("c1", {}),
-    ("c1-haar-untruncated", dict(wavelet="haar")),
-    ("c2", {}),
-    ("c2-small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
-    ("c2-tiny", dict(subdiv=0, keep=0.5)),
-    ("c2-batched", dict(subdiv=4, n_light=5, n_cfg=5)),
-    ("c3", {}),
-    ("c3-f32", dict(storage="f32", wavelet="haar", keep=None)),
-    ("c4-shrunk", dict(subdiv=4, n_light=64, n_cfg=64)),
-    ("c5-shrunk", dict(subdiv=4, n_light=16, n_cfg=1, sample_rows=0)),
+    ("dense-f64-642", {}),
+    ("dense-f64-642:haar-untruncated", dict(wavelet="haar")),
+    ("haar-f32-10242", {}),
+    ("haar-f32-10242:small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
+    ("haar-f32-10242:tiny", dict(subdiv=0, keep=0.5)),
+    ("haar-f32-10242:batched", dict(subdiv=4, n_light=5, n_cfg=5)),
+    ("grad-f64-642", {}),
+    ("grad-f64-642:f32", dict(storage="f32", wavelet="haar", keep=None)),
+    ("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=64, n_cfg=64)),
+    ("large-f16-163842:shrunk", dict(subdiv=4, n_light=16, n_cfg=1, sample_rows=0)),
 ]
 
 
 def _workload(name, kw):
-    return synth.get(name.split("-")[0]).with_(**kw)
+    return synth.get(name.split(":")[0]).with_(**kw)
 
 
 @pytest.mark.parametrize("name,kw", CASES, ids=[c[0] for c in CASES])
@@ -74,7 +74,7 @@ def test_render_matches_oracle(name, kw):
 
 def test_untruncated_wavelet_equals_plain_fp64():
     """Eq. (8): with nothing truncated the Haar form equals the plain form."""
-    w = synth.get("c1")
+    w = synth.get("dense-f64-642")
     say("[parity] untruncated haar vs plain, FP64")
     r1, L, th, B1 = _render(w)
     r2, _, _, B2 = _render(w.with_(wavelet="haar"), L, th)
@@ -84,8 +84,8 @@ def test_untruncated_wavelet_equals_plain_fp64():
 
 
 def test_stored_rows_match_host_build_and_oracle():
-    w = synth.get("c2").with_(subdiv=4)
-    say("[rows] c2 subdiv 4")
+    w = synth.get("haar-f32-10242").with_(subdiv=4)
+    say("[rows] haar-f32 subdiv 4")
     r = renderer_for(w)
     o = oracle_scene(w)
     m_rows = np.arange(0, w.n_vertices, 61)
@@ -100,7 +100,7 @@ def test_stored_rows_match_host_build_and_oracle():
 
 
 def test_intermediates_ehat_and_weights():
-    w = synth.get("c2").with_(subdiv=4, n_light=2, n_cfg=2)
+    w = synth.get("haar-f32-10242").with_(subdiv=4, n_light=2, n_cfg=2)
     say("[intermediates] Ehat, g, dg")
     r, L, th, _ = _render(w)
     o = oracle_scene(w)
@@ -116,7 +116,7 @@ def test_intermediates_ehat_and_weights():
 
 
 def test_linearity_and_material_only_update():
-    w = synth.get("c2").with_(subdiv=4, n_light=3, n_cfg=1)
+    w = synth.get("haar-f32-10242").with_(subdiv=4, n_light=3, n_cfg=1)
     say("[invariants] linearity, material-only update")
     L = synth.make_lighting(w)
     L[2] = 2 * L[0] - 0.5 * L[1]
@@ -138,8 +138,8 @@ def test_autograd_c3_fp64_gradients():
     """Gradient of the L2 loss vs the FP64 oracle adjoint and central FD."""
     from oracle import adjoint
     from paper_2203_12339_amd.autograd import render as trender
-    w = synth.get("c3")
-    say("[grad] c3 FP64")
+    w = synth.get("grad-f64-642")
+    say("[grad] grad-f64-642")
     o = oracle_scene(w)
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
@@ -159,14 +159,14 @@ def test_autograd_c3_fp64_gradients():
     fL, fT = adjoint.fd_grad(o, L, th, Bt)
     np.testing.assert_allclose(gL, fL, rtol=1e-5, atol=1e-8 * np.abs(fL).max())
     np.testing.assert_allclose(gT, fT, rtol=1e-5, atol=1e-8 * np.abs(fT).max())
-    say(f"[grad] c3 FP64 ok |gL|={np.abs(gL).max():.3e} |gT|={np.abs(gT).max():.3e}")
+    say(f"[grad] grad-f64-642 ok |gL|={np.abs(gL).max():.3e} |gT|={np.abs(gT).max():.3e}")
     r.close()
 
 
-@pytest.mark.parametrize("name,kw", [("c3-f32", dict(storage="f32", wavelet="haar")),
-                                     ("c2-batched", dict(subdiv=3, n_light=4, n_cfg=4)),
-                                     ("c5-shrunk", dict(subdiv=3, n_light=6, n_cfg=1))],
-                         ids=["c3-f32", "c2-batched", "c5-shrunk"])
+@pytest.mark.parametrize("name,kw", [("grad-f64-642:f32", dict(storage="f32", wavelet="haar")),
+                                     ("haar-f32-10242:batched", dict(subdiv=3, n_light=4, n_cfg=4)),
+                                     ("large-f16-163842:shrunk", dict(subdiv=3, n_light=6, n_cfg=1))],
+                         ids=["grad-f64-642:f32", "haar-f32-10242:batched", "large-f16-163842:shrunk"])
 def test_adjoint_fp32_matches_oracle(name, kw):
     from oracle import adjoint
     w = _workload(name, kw)
@@ -197,7 +197,7 @@ def test_adjoint_fp32_matches_oracle(name, kw):
 
 
 def test_error_paths_on_device():
-    w = synth.get("c2").with_(subdiv=2)
+    w = synth.get("haar-f32-10242").with_(subdiv=2)
     say("[errors] status codes")
     r = tlt.Renderer(0)
     with pytest.raises(tlt.TltError) as ei:

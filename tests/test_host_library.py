@@ -37,10 +37,10 @@ def test_library_exports_every_declared_function():
     assert "gfx950" in tlt.version()
 
 
-@pytest.mark.parametrize("name", ["c1", "c2", "c5"])
+@pytest.mark.parametrize("name", ["dense-f64-642", "haar-f32-10242", "large-f16-163842"])
 def test_prepare_scene_matches_oracle(name):
     w = synth.get(name)
-    if name == "c5":
+    if name == "large-f16-163842":
         w = w.with_(subdiv=4)
     sc = scene_for(w)
     o = Scene(w)
@@ -56,13 +56,13 @@ def test_prepare_scene_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name,kw", [
-    ("c2", {}),
-    ("c1", {}),
-    ("c1", dict(wavelet="haar")),
-    ("c4", dict(subdiv=4)),
-    ("c5", dict(subdiv=3)),
-    ("c2", dict(subdiv=0, keep=0.5)),
-], ids=["c2", "c1-plain", "c1-haar-full", "c4-shrunk", "c5-shrunk", "tiny"])
+    ("haar-f32-10242", {}),
+    ("dense-f64-642", {}),
+    ("dense-f64-642", dict(wavelet="haar")),
+    ("batch64-bf16-40962", dict(subdiv=4)),
+    ("large-f16-163842", dict(subdiv=3)),
+    ("haar-f32-10242", dict(subdiv=0, keep=0.5)),
+], ids=["haar-f32-10242", "dense-f64-642:plain", "dense-f64-642:haar-full", "batch64-bf16-40962:shrunk", "large-f16-163842:shrunk", "tiny"])
 def test_build_rows_match_oracle(name, kw):
     w = synth.get(name).with_(**kw)
     sc = scene_for(w)

@@ -170,7 +170,7 @@ def test_icosahedron_areas_golden():
 
 def test_mesh_sizes_and_areas():
     for s, n in [(0, 12), (1, 42), (2, 162), (3, 642)]:
-        w = synth.get("c1").with_(subdiv=s)
+        w = synth.get("dense-f64-642").with_(subdiv=s)
         V, F = synth.make_mesh(w)
         assert V.shape[0] == n == w.n_vertices
         A = geometry.vertex_areas(V, F)
@@ -196,7 +196,7 @@ def test_morton_hand_example_and_bijection():
     assert int(k[0]) == (1 << 63) - 1
     assert top == 2097151
     assert list(geometry.morton_perm(V)) == [1, 3, 2, 0]
-    V, F = synth.make_mesh(synth.get("c2"))
+    V, F = synth.make_mesh(synth.get("haar-f32-10242"))
     p = geometry.morton_perm(V)
     assert np.array_equal(np.sort(p), np.arange(V.shape[0]))
     keys = geometry.morton_keys(V)[p]
@@ -245,7 +245,7 @@ def test_haar_orthonormal_and_inverse():
 # --------------------------------------------------------------------------
 
 def test_pca_full_rank_and_eckart_young():
-    w = synth.get("c2")
+    w = synth.get("haar-f32-10242")
     rn = pca.r_nodes(w.r_max)
     mats = pca.material_grid(synth.MATERIAL_GRID)
     M = pca.table(rn, mats)
@@ -266,7 +266,7 @@ def test_pca_full_rank_and_eckart_young():
 
 
 def test_weight_grads_complex_step():
-    w = synth.get("c1")
+    w = synth.get("dense-f64-642")
     rn = pca.r_nodes(w.r_max)
     M = pca.table(rn, pca.material_grid(synth.MATERIAL_GRID))
     b, _ = pca.basis(M, 8)
@@ -284,7 +284,7 @@ def test_weight_grads_complex_step():
 # --------------------------------------------------------------------------
 
 def _small(wavelet, subdiv=2, **kw):
-    w = synth.get("c1").with_(subdiv=subdiv, wavelet=wavelet, keep=None, **kw)
+    w = synth.get("dense-f64-642").with_(subdiv=subdiv, wavelet=wavelet, keep=None, **kw)
     return w, Scene(w, K=256)
 
 
@@ -308,7 +308,7 @@ def test_uniform_sphere_converges_to_closed_form():
     th = np.array([[[0.01, 1.0, 1.3]] * 3])
     errs = []
     for s_ in (2, 3, 4):
-        w = synth.get("c1").with_(subdiv=s_, noise=0.0, n_sh=1, wavelet="none")
+        w = synth.get("dense-f64-642").with_(subdiv=s_, noise=0.0, n_sh=1, wavelet="none")
         sc = Scene(w, K=4)
         L = np.zeros((1, 1, 3))
         L[0, 0, :] = 1.0
@@ -322,7 +322,7 @@ def test_uniform_sphere_converges_to_closed_form():
 
 
 def test_linearity_and_reciprocity():
-    w = synth.get("c1").with_(subdiv=2, n_light=3, n_cfg=1, keep=None, wavelet="haar")
+    w = synth.get("dense-f64-642").with_(subdiv=2, n_light=3, n_cfg=1, keep=None, wavelet="haar")
     s = Scene(w)
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
@@ -341,7 +341,7 @@ def test_linearity_and_reciprocity():
 
 
 def test_selection_matches_brute_force_sort():
-    w = synth.get("c1").with_(subdiv=1, keep=0.25, wavelet="haar")
+    w = synth.get("dense-f64-642").with_(subdiv=1, keep=0.25, wavelet="haar")
     s = Scene(w)
     rng = np.random.default_rng(3)
     Wr = rng.integers(-4, 5, size=(3, 7, 64)).astype(float)   # many ties
@@ -354,7 +354,7 @@ def test_selection_matches_brute_force_sort():
 
 
 def test_truncation_keeps_the_largest_and_reduces_to_dense():
-    w = synth.get("c2").with_(subdiv=3, keep=0.05)
+    w = synth.get("haar-f32-10242").with_(subdiv=3, keep=0.05)
     s = Scene(w)
     cols, vals = s.kept_lists(np.arange(0, s.N, 37))
     assert cols.shape[-1] == w.n_keep == round(0.05 * 642)
@@ -373,7 +373,7 @@ def test_truncation_keeps_the_largest_and_reduces_to_dense():
 # --------------------------------------------------------------------------
 
 def test_adjoint_dot_product_and_fd():
-    w = synth.get("c3").with_(subdiv=1, wavelet="haar", keep=0.3)
+    w = synth.get("grad-f64-642").with_(subdiv=1, wavelet="haar", keep=0.3)
     s = Scene(w)
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
@@ -402,7 +402,7 @@ def test_adjoint_dot_product_and_fd():
 
 
 def test_adjoint_on_sampled_rows_equals_masked_full():
-    w = synth.get("c2").with_(subdiv=2, keep=0.1, n_light=2, n_cfg=2)
+    w = synth.get("haar-f32-10242").with_(subdiv=2, keep=0.1, n_light=2, n_cfg=2)
     s = Scene(w)
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
