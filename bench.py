@@ -33,8 +33,10 @@ def log(*a):
 
 
 def kernel_hash():
+    """Hash of the library sources: stored counter readings are valid only
+    for the kernels and data layout they were taken on."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.h"):
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2203_12339_amd", "csrc"))):
         with open(os.path.join(ROOT, "paper_2203_12339_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -178,7 +180,7 @@ def main():
     traffic = stored_traffic(w.name, C)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_transport",
+                "traffic": traffic, "kernel": "k_stream" if args.plain else "k_tiles",
                 "kernel_us": round(avg_s * 1e6, 2), "algorithmic_bytes": alg_bytes}
     flops = 2.0 * nnz * C
     ai = flops / alg_bytes

@@ -1,4 +1,4 @@
-// Small kernels: material-only combine, adjoint reductions (a6), storage
+// Small kernels: material-only combine, adjoint reductions, storage
 // conversion at load time.
 
 #include "device_common.h"
@@ -35,7 +35,7 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
 }
 
 // ---------------------------------------------------------------------------
-// a6: adjoint.
+// Adjoint of the transport.
 //
 //   gbar[k][c]  = sum_o dB[c](perm[o]) * V[k][o][c]
 //   X[c][lm]    = sum_o dB[c](perm[o]) * sum_k g[k][c] P[k][o][lm]

@@ -1,8 +1,8 @@
 // Per-frame preparation in ONE launch (heterogeneous workgroups):
 //
-//   [0, n_gk)              a1: material weights g_k and dg_k/dtheta (float64),
+//   [0, n_gk)              material weights g_k and dg_k/dtheta (float64),
 //                              rendering Step 3 of Sec. 4 with Eq. (4);
-//   [n_gk, n_gk + n_tl)    a2+a3: E = T L on MFMA, times area, Haar levels
+//   [n_gk, n_gk + n_tl)    E = T L on MFMA, times area, Haar levels
 //                              inside a 256-row chunk (Step 1, Eq. 6 and 8);
 //   [.., + n_zero)         clears B at the vertices whose rows the
 //                              transport kernel splits between two waves.
@@ -22,7 +22,7 @@
 namespace tlt {
 
 // ---------------------------------------------------------------------------
-// a1: dipole R_d (Eq. 4) with its parameter derivatives.
+// Material weights: dipole R_d (Eq. 4) with its parameter derivatives.
 // ---------------------------------------------------------------------------
 
 struct RdGrad {
@@ -130,7 +130,7 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
 }
 
 // ---------------------------------------------------------------------------
-// a2 + a3.
+// Irradiance E = T L, area weight and the Haar levels inside a chunk.
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
 
 size_t prep_lds_bytes(const PrepArgs &a) {
   const size_t esz = a.fp64 ? 8 : 4;
-  size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // a1
+  size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // material weights
   s = std::max(s, (size_t)TL_CH * TL_STRIDE * esz);
   return s;
 }

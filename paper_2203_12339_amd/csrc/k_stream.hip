@@ -1,4 +1,4 @@
-// a4 + a5: wavelet-sparse transport with K-term fusion (Eq. 7 and 8,
+// Wavelet-sparse transport with K-term fusion (Eq. 7 and 8,
 // rendering Steps 2 and 4 of Sec. 4), streamed row by row.
 //
 // The rows (o, k) of the transport are contiguous in memory (row = o*K+k),

@@ -1,4 +1,4 @@
-// a4 + a5 on block-dense tiles: the wavelet-sparse transport of Eq. (7)/(8)
+// Block-dense tiles: the wavelet-sparse transport of Eq. (7)/(8)
 // (rendering Steps 2 and 4 of Sec. 4) as 16x16 matrix-instruction tiles.
 //
 // A block holds the R = V*K rows (o, k) of V Morton-consecutive vertices,

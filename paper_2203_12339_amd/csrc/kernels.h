@@ -20,15 +20,15 @@ struct Cols {
   int n_mat;
 };
 
-// One launch for a1 (material weights), a2+a3 (irradiance and its Haar
-// transform) and the clearing of split output vertices; any part may be
+// One launch for the material weights, the irradiance with its Haar
+// transform, and the clearing of split output vertices; any part may be
 // switched off by a zero block count.
 struct PrepArgs {
   bool fp64;
   int tdt;                 // transfer storage (tlt.h codes)
   int Cs;                  // column stride of Ehat and gcol
   Cols cols;
-  // a1
+  // material weights g_k
   int n_gk_blocks;         // n_mat * 3, or 0
   const double *theta;     // [n_mat][3][3]
   const double *rn;        // [nr]
@@ -36,7 +36,7 @@ struct PrepArgs {
   int nr, K;
   double *g64, *dg64;      // [n_mat][3][K], [n_mat][3][K][3]
   void *gcol;              // [K][Cs] compute precision
-  // a2 + a3
+  // irradiance E = T L and its Haar transform
   int n_tl_blocks;         // n_chunks * Cs/16, or 0
   const void *T;           // [N][n_sh] storage tdt
   int N, n_sh, n_shp;
@@ -56,7 +56,7 @@ struct PrepArgs {
 hipError_t launch_prep(const PrepArgs &a, hipStream_t st);
 size_t prep_lds_bytes(const PrepArgs &a);
 
-// a4 + a5: streamed wavelet-sparse transport with K-term fusion.
+// Transport: streamed wavelet-sparse rows with K-term fusion.
 struct StreamArgs {
   const int32_t *col;      // [N*K][n_keep]
   const void *val;         // [N*K][n_keep] storage
@@ -78,7 +78,7 @@ hipError_t launch_stream(StreamArgs a, int vdt, bool fp64, int cpl, hipStream_t 
 bool stream_cpl_supported(int cpl);
 int stream_waves(int N, int K, int waves_per_cu);
 
-// a4 + a5 on block-dense tiles (16-bit or f32 storage, f32 compute).
+// Transport on block-dense tiles (16-bit or f32 storage, f32 compute).
 struct TileArgs {
   const int64_t *blk_off;  // [n_blocks+1] union offsets
   const int32_t *ucol;     // union column ids
@@ -102,7 +102,7 @@ int tile_kstep(int vdt);
 hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
                           const int32_t *perm, void *B, bool fp64, hipStream_t st);
 
-// a6: partial sums over vertex blocks, then the final reduction.
+// Adjoint: partial sums over vertex blocks, then the final reduction.
 hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, int Psh,
                           const void *gcol, const double *dg64, const int32_t *perm, int N, int K,
                           int n_sh, Cols cols, bool fp64, void *partial, size_t partial_bytes,

@@ -134,7 +134,7 @@ def test_linearity_and_material_only_update():
     r.close()
 
 
-def test_autograd_c3_fp64_gradients():
+def test_autograd_fp64_gradients():
     """Gradient of the L2 loss vs the FP64 oracle adjoint and central FD."""
     from oracle import adjoint
     from paper_2203_12339_amd.autograd import render as trender
