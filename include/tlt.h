@@ -108,8 +108,9 @@ typedef struct {
 tlt_status tlt_prepare_scene(tlt_scene *scene);
 
 /*
- * Host-only: the float64 transport rows that load_transport builds when
- * desc->col == NULL, for selected output points.  For each of the n_rows
+ * Host-only: the float64 transport rows for selected output points -- the
+ * same rows, operation for operation, that load_transport builds on the
+ * device when desc->col == NULL (usable to precompute rows offline).  For each of the n_rows
  * Morton positions rows[i] and each k < K, writes the n_keep kept (column,
  * value) pairs of row (rows[i], k) to col_out/val_out [n_rows][K][n_keep],
  * columns ascending (precompute Step 1 of Sec. 3.2; Eq. 7 and 8).
@@ -135,8 +136,11 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  * btilde_k(|x_o - x_j|): the basis b_k interpolated linearly between the
  * r nodes, i.e. the area weight is applied to the irradiance side.
  *
- * col == NULL: the rows are computed here in float64 from `position`,
- *   `r_nodes` and `basis` (n_keep <= n_cols), then stored in value_dtype.
+ * col == NULL: the rows are computed on the device in float64 from
+ *   `position`, `r_nodes` and `basis`, then stored in value_dtype (rounded
+ *   to nearest even, 16-bit types via float32).  Supported for n_cols <=
+ *   2^20 with n_keep == n_cols or n_keep <= 8192, else TLT_E_ARG; a failed
+ *   internal consistency check of the selection gives TLT_E_STATE.
  * col != NULL: col/val are taken as given (val in value_dtype); every
  *   column is checked to lie in [0, n_cols) and rows to ascend, else
  *   TLT_E_FORMAT.

@@ -46,10 +46,12 @@ def grad(scene, L, theta, Bbar, rows=None, block=64):
     for s in range(0, len(rows), block):
         pr = rows[s:s + block]
         bb = Bb[:, s:s + len(pr), :]                     # [n_out, P, 3]
-        Wt, _ = scene.truncated_rows(pr)                 # [K, P, n]
-        v = np.einsum("kpj,qjc->kqpc", Wt, Eh)
+        cols, vals = scene.kept_lists(pr)                # [K, P, nk]
+        v = np.einsum("kpn,qkpnc->kqpc", vals, Eh[:, cols, :])
         gbar += np.einsum("qpc,kqpc->qck", bb, v)
-        ehbar += np.einsum("qck,kpj,qpc->qjc", G, Wt, bb)
+        # each kept W_k[p, j] sends g_k Bbar[p] back to column j
+        contrib = np.einsum("qck,kpn,qpc->qkpnc", G, vals, bb)
+        np.add.at(ehbar, (slice(None), cols.reshape(-1)), contrib.reshape(w.n_out, -1, 3))
     thbar = np.zeros((w.n_cfg, 3, 3))
     for q in range(w.n_out):
         thbar[mat_of(w, q)] += np.einsum("ck,ckp->cp", gbar[q], dg[mat_of(w, q)])

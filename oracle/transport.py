@@ -131,6 +131,11 @@ class Scene:
         vals = np.take_along_axis(Wt, cols, axis=-1)
         return cols, vals
 
+    def transport(self, p_rows, Eh):
+        """v[k, q, p, ch] = sum over j in S(p, k) of W_k[p, j] Ehat[q, j, ch]."""
+        cols, vals = self.kept_lists(p_rows)            # [K, P, nk]
+        return np.einsum("kpn,qkpnc->kqpc", vals, Eh[:, cols, :])
+
     # -- radiance ---------------------------------------------------------
     def render_rows(self, L, theta, p_rows, block=64, keep_v=False):
         """O-B radiance at Morton positions p_rows -> B[q, len(p_rows), ch].
@@ -146,8 +151,7 @@ class Scene:
         V = np.zeros((self.K, w.n_out, len(p_rows), 3)) if keep_v else None
         for s in range(0, len(p_rows), block):
             pr = p_rows[s:s + block]
-            Wt, _ = self.truncated_rows(pr)             # [K, P, n]
-            v = np.einsum("kpj,qjc->kqpc", Wt, Eh)      # [K, n_out, P, 3]
+            v = self.transport(pr, Eh)                  # [K, n_out, P, 3]
             B[:, s:s + len(pr), :] = np.einsum("qck,kqpc->qpc", G, v)
             if keep_v:
                 V[:, :, s:s + len(pr), :] = v

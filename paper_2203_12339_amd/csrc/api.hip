@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -165,14 +167,6 @@ void free_all(tlt_ctx *c) {
   c->sh = nullptr;
   c->theta = nullptr;
   c->n_light = c->n_mat = 0;
-}
-
-int host_threads() {
-  const char *e = std::getenv("TLT_THREADS");
-  if (e && std::atoi(e) > 0) return std::atoi(e);
-  unsigned h = std::thread::hardware_concurrency();
-  if (h == 0) h = 4;
-  return (int)std::min<unsigned>(h, 16);
 }
 
 // (Re)allocates every buffer whose size depends on the column count.
@@ -499,6 +493,151 @@ tlt_status tlt_set_tile(tlt_ctx *c, int cpl) {
 
 int tlt_get_tile(const tlt_ctx *c) { return c ? c->cpl : 0; }
 
+// Transport rows built on the device from the Morton-ordered positions
+// (kernel rows, Haar transform and exact top-n per row), in batches of
+// vertices whose unsorted kept entries fit a bounded scratch buffer.
+tlt_status device_build_rows(tlt_ctx *c, const tlt_transport_desc *d, int n_cols) {
+  const int N = c->N, K = c->K, nr = c->nr;
+  const int64_t n_keep = d->n_keep;
+  const bool all = n_keep == n_cols;
+  if (!all && n_keep > build_sort_max())
+    return fail(&c->err, TLT_E_ARG,
+                "device build keeps at most " + std::to_string(build_sort_max()) +
+                    " coefficients per row (or all); pass rows built on the host");
+  if (n_cols > (1 << 20)) return fail(&c->err, TLT_E_ARG, "device build supports at most 2^20 columns");
+  if (c->wavelet == TLT_WAVELET_HAAR && n_cols < 8)
+    return fail(&c->err, TLT_E_ARG, "device build of Haar rows needs n_pad >= 8");
+  const int chw = std::min(n_cols, build_chunk_columns());
+  const int max_chunks = (n_cols + chw - 1) / chw;
+  std::vector<double> slope((size_t)K * nr, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int m = 0; m + 1 < nr; ++m)
+      slope[(size_t)k * nr + m] =
+          (d->basis[(size_t)k * nr + m + 1] - d->basis[(size_t)k * nr + m]) / (d->r_nodes[m + 1] - d->r_nodes[m]);
+  double *pos = nullptr, *dsl = nullptr, *sval = nullptr;
+  int32_t *scol = nullptr;
+  int *status = nullptr;
+  tlt_status s = TLT_OK;
+  hipError_t he = hipSuccess;
+  const int64_t per_v = (int64_t)K * n_keep;
+  const bool verbose = std::getenv("TLT_VERBOSE") != nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  int64_t nvb = all ? N : std::max<int64_t>(1, ((int64_t)256 << 20) / (per_v * 12));
+  nvb = std::min<int64_t>(nvb, N);
+  if ((s = dalloc(c, (void **)&pos, sizeof(double) * 3 * (size_t)N, "positions")) != TLT_OK) goto out;
+  if ((s = dalloc(c, (void **)&dsl, sizeof(double) * slope.size(), "slopes")) != TLT_OK) goto out;
+  if ((s = dalloc(c, (void **)&status, sizeof(int), "build status")) != TLT_OK) goto out;
+  if (!all) {
+    if ((s = dalloc(c, (void **)&scol, sizeof(int32_t) * (size_t)(nvb * per_v), "build scratch")) != TLT_OK) goto out;
+    if ((s = dalloc(c, (void **)&sval, sizeof(double) * (size_t)(nvb * per_v), "build scratch")) != TLT_OK) goto out;
+  }
+#define BTRY(x) if ((he = (x)) != hipSuccess) { s = hip_fail(c, he, #x); goto out; }
+  BTRY(hipMemcpy(pos, d->position, sizeof(double) * 3 * (size_t)N, hipMemcpyHostToDevice));
+  BTRY(hipMemcpy(dsl, slope.data(), sizeof(double) * slope.size(), hipMemcpyHostToDevice));
+  BTRY(hipMemset(status, 0, sizeof(int)));
+  for (int64_t o0 = 0; o0 < N; o0 += nvb) {
+    if (verbose && o0 == 0) std::fprintf(stderr, "[tlt] building transport rows on the device\n");
+    BuildArgs a{};
+    a.pos = pos;
+    a.rn = c->rn;
+    a.basis = c->basis;
+    a.slope = dsl;
+    a.N = N;
+    a.n_cols = n_cols;
+    a.K = K;
+    a.nr = nr;
+    a.haar = c->wavelet == TLT_WAVELET_HAAR;
+    a.hsq = 1.0 / std::sqrt(2.0);
+    a.n_keep = n_keep;
+    a.o0 = (int)o0;
+    a.nv = (int)std::min<int64_t>(nvb, N - o0);
+    a.all = all;
+    a.max_chunks = max_chunks;
+    a.scol = scol;
+    a.sval = sval;
+    a.col = c->col;
+    a.val = c->val;
+    a.vdt = c->vdt;
+    a.status = status;
+    for (int kg0 = 0; kg0 < K; kg0 += build_max_group()) {
+      a.kg0 = kg0;
+      BTRY(launch_build_select(a, std::min(build_max_group(), K - kg0), 0));
+    }
+    if (!all) BTRY(launch_build_sort(a, 0));
+    if (verbose) {
+      BTRY(hipDeviceSynchronize());
+      std::fprintf(stderr, "[tlt] transport rows: %lld / %d vertices, %.1f s\n",
+                   (long long)(o0 + a.nv), N,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    }
+  }
+  BTRY(hipDeviceSynchronize());
+  {
+    int h = 0;
+    BTRY(hipMemcpy(&h, status, sizeof(int), hipMemcpyDeviceToHost));
+    if (h != 0) s = fail(&c->err, TLT_E_STATE, "device transport build failed its checks (" + std::to_string(h) + ")");
+  }
+#undef BTRY
+out:
+  dfree(pos);
+  dfree(dsl);
+  dfree(status);
+  dfree(scol);
+  dfree(sval);
+  return s;
+}
+
+// Block-dense tiles from the device rows: union sizes per block, offsets on
+// the host, then union ids and operand-ordered values.
+tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
+  const int nb = (c->N + tV - 1) / tV;
+  TileBuildArgs a{};
+  a.col = c->col;
+  a.val = c->val;
+  a.esz = (int)dtype_size(c->vdt);
+  a.N = c->N;
+  a.K = c->K;
+  a.V = tV;
+  a.n_keep = c->n_keep;
+  a.n_words = (n_cols + 31) / 32;
+  a.n_blocks = nb;
+  a.kstep = tile_kstep(c->vdt);
+  int64_t *cnt = nullptr, *off = nullptr;
+  tlt_status s = TLT_OK;
+  hipError_t he = hipSuccess;
+  std::vector<int64_t> h(nb), ho(nb + 1, 0);
+  if ((s = dalloc(c, (void **)&cnt, sizeof(int64_t) * nb, "tile counts")) != TLT_OK) return s;
+#define BTRY(x) if ((he = (x)) != hipSuccess) { s = hip_fail(c, he, #x); goto out; }
+  a.count = cnt;
+  BTRY(launch_tile_count(a, 0));
+  BTRY(hipMemcpy(h.data(), cnt, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
+  c->t_max_union = 0;
+  for (int b = 0; b < nb; ++b) {
+    ho[b + 1] = ho[b] + h[b];
+    c->t_max_union = std::max<int>(c->t_max_union, (int)h[b]);
+  }
+  c->tV = tV;
+  c->tR = tV * c->K;
+  c->t_blocks = nb;
+  c->t_val_bytes = (size_t)ho[nb] * c->tR * a.esz;
+  if ((s = dalloc(c, (void **)&c->t_off, sizeof(int64_t) * (nb + 1), "tile offsets")) != TLT_OK) goto out;
+  if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * (size_t)ho[nb], "tile columns")) != TLT_OK) goto out;
+  if ((s = dalloc(c, &c->t_val, c->t_val_bytes, "tile values")) != TLT_OK) goto out;
+  BTRY(hipMemcpy(c->t_off, ho.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
+  BTRY(hipMemset(c->t_val, 0, c->t_val_bytes));
+  a.blk_off = c->t_off;
+  a.ucol = c->t_ucol;
+  a.tval = c->t_val;
+  BTRY(launch_tile_fill(a, 0));
+  BTRY(hipDeviceSynchronize());
+  c->tiles = true;
+#undef BTRY
+out:
+  dfree(cnt);
+  (void)off;
+  return s;
+}
+
 tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   if (!c || !d) return fail(c ? &c->err : nullptr, TLT_E_ARG, "NULL argument");
   HIPC(c, hipSetDevice(c->device));
@@ -573,10 +712,13 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   const size_t vsz = dtype_size(c->vdt);
   const size_t nnz = (size_t)n_rowsW * (size_t)d->n_keep;
   const int tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K);
-  const bool tiles_ok = tV > 0 && tV * d->K >= 64 && tV * d->K <= 128 && (tV * d->K) % 16 == 0;
+  // (the tile build keeps two bitmaps of n_cols bits in LDS)
+  const bool tiles_ok = tV > 0 && tV * d->K >= 64 && tV * d->K <= 128 && (tV * d->K) % 16 == 0 &&
+                        (size_t)8 * ((n_cols + 31) / 32) <= (size_t)150 * 1024;
   const bool want_tiles = !c->fp64 && d->layout != TLT_LAYOUT_ROWS && tiles_ok;
   if (d->layout == TLT_LAYOUT_TILES && (c->fp64 || !tiles_ok)) {
-    s = fail(&c->err, TLT_E_ARG, "tiles need non-F64 storage and 64 <= V*K <= 128, V*K % 16 == 0");
+    s = fail(&c->err, TLT_E_ARG,
+             "tiles need non-F64 storage, 64 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
     goto fail_all;
   }
   if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
@@ -617,69 +759,16 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
     };
     he = upload_q(d->transfer, c->T, c->tdt, (size_t)N * c->n_sh);
     if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transfer"); goto fail_all; }
-    // Rows are built (or taken) in chunks of vertices; each chunk is uploaded
-    // as (column, value) rows and, when tiles are wanted, appended to them.
-    const int nth = host_threads();
-    const int64_t per_row = (int64_t)c->K * d->n_keep;
-    int64_t vb = std::max<int64_t>(1, (int64_t)(96 << 20) / std::max<int64_t>(1, per_row * 12));
-    if (want_tiles) vb = std::max<int64_t>(tV, vb / tV * tV);
-    vb = std::min<int64_t>(vb, N);
-    TileBuild tb;
-    tb.V = tV;
-    tb.K = c->K;
-    tb.kstep = tile_kstep(c->vdt);
-    std::vector<int32_t> hc;
-    std::vector<double> hv;
-    try {
-      if (!d->col) hc.resize((size_t)(vb * per_row));
-      if (!d->col || want_tiles) hv.resize((size_t)(vb * per_row));
-    } catch (...) {
-      dfree(stage);
-      s = fail(&c->err, TLT_E_OOM, "host staging for the transport build");
+    dfree(stage);
+    // Rows given by the caller are uploaded as they are; otherwise they are
+    // built on the device.  Tiles are then built on the device from the rows.
+    if (d->col) {
+      HTRY(hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+      HTRY(hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice));
+    } else if ((s = device_build_rows(c, d, n_cols)) != TLT_OK) {
       goto fail_all;
     }
-    for (int64_t o0 = 0; o0 < N; o0 += vb) {
-      const int64_t nv = std::min<int64_t>(vb, N - o0);
-      const size_t off = (size_t)(o0 * per_row);
-      const size_t m = (size_t)(nv * per_row);
-      const int32_t *ccol;
-      if (d->col) {
-        ccol = d->col + off;
-        he = hipMemcpy(c->col + off, ccol, sizeof(int32_t) * m, hipMemcpyHostToDevice);
-        if (he == hipSuccess)
-          he = hipMemcpy((char *)c->val + off * vsz, (const char *)d->val + off * vsz, vsz * m,
-                         hipMemcpyHostToDevice);
-        if (want_tiles)
-          for (size_t e = 0; e < m; ++e) hv[e] = widen(d->val, c->vdt, off + e);
-      } else {
-        host_build_rows((int)nv, n_cols, c->K, c->nr, c->wavelet, d->n_keep, d->position + 3 * o0,
-                        d->r_nodes, d->basis, hc.data(), hv.data(), nth, N, d->position);
-        ccol = hc.data();
-        he = hipMemcpy(c->col + off, hc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice);
-        if (he == hipSuccess) he = upload_q(hv.data(), (char *)c->val + off * vsz, c->vdt, m);
-      }
-      if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading the transport"); goto fail_all; }
-      if (want_tiles) tiles_append(tb, (int)nv, n_cols, d->n_keep, ccol, hv.data(), c->vdt, nth);
-    }
-    dfree(stage);
-    if (want_tiles) {
-      c->tiles = true;
-      c->tV = tV;
-      c->tR = tV * c->K;
-      c->t_blocks = (int)tb.n_blocks;
-      for (int64_t bb = 0; bb < tb.n_blocks; ++bb)
-        c->t_max_union = std::max<int>(c->t_max_union, (int)(tb.blk_off[bb + 1] - tb.blk_off[bb]));
-      const size_t nu = tb.ucol.size();
-      const size_t nvals = nu * (size_t)c->tR;
-      c->t_val_bytes = nvals * (c->vdt == TLT_F32 ? 4 : 2);
-      if ((s = dalloc(c, (void **)&c->t_off, sizeof(int64_t) * tb.blk_off.size(), "tile offsets")) != TLT_OK) goto fail_all;
-      if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * nu, "tile columns")) != TLT_OK) goto fail_all;
-      if ((s = dalloc(c, &c->t_val, c->t_val_bytes, "tile values")) != TLT_OK) goto fail_all;
-      HTRY(hipMemcpy(c->t_off, tb.blk_off.data(), sizeof(int64_t) * tb.blk_off.size(), hipMemcpyHostToDevice));
-      HTRY(hipMemcpy(c->t_ucol, tb.ucol.data(), sizeof(int32_t) * nu, hipMemcpyHostToDevice));
-      HTRY(hipMemcpy(c->t_val, c->vdt == TLT_F32 ? (const void *)tb.v32.data() : (const void *)tb.v16.data(),
-                     c->t_val_bytes, hipMemcpyHostToDevice));
-    }
+    if (want_tiles && (s = device_build_tiles(c, tV, n_cols)) != TLT_OK) goto fail_all;
 #undef HTRY
   }
   if ((s = ensure_partition(c)) != TLT_OK) goto fail_all;

@@ -41,6 +41,14 @@ template <> __device__ __forceinline__ float ld_nt<f16s, float>(const f16s *p, i
   return (float)__builtin_bit_cast(_Float16, u);
 }
 
+// float32 -> bfloat16, rounded to nearest even.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);

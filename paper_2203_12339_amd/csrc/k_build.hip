@@ -1,0 +1,652 @@
+// Load-time construction of the transport on the device: precompute Step 1
+// (listed at the end of Sec. 3.2) -- for every output vertex o and basis term k the kernel row
+// btilde_k(|x_o - x_i|) over the Morton-ordered vertices, its orthonormal
+// Haar transform (Eq. 8) and the n_keep coefficients of largest magnitude
+// (ties to the lower column) -- followed by the block-dense tiles of the
+// transport kernel.  Everything is float64 until the final store, and the
+// arithmetic is written operation for operation like the host builder
+// (no fused multiply-adds), so both produce the same rows.
+//
+// Selection.  A row of n_cols coefficients never exists in memory: a
+// workgroup regenerates the rows of one vertex (all k of its group) in
+// chunks of 4096 columns, pass after pass.  Each pass is a step of an exact
+// radix select on the compound key (|w| as an ordered integer, then the
+// inverted column index), 9 bits at a time: a histogram of the entries
+// inside the current key range tells which bin holds the n_keep-th largest
+// entry; the range narrows to that bin.  Once the range holds at most CAP
+// entries, one more pass writes every entry above the range and keeps the
+// range's entries in LDS, where they are ranked exactly.  Histogram and
+// counter updates are aggregated per wave (one atomic per distinct bin),
+// because neighbouring coefficients of one level fall in the same bins.
+// The kept entries are written unordered, then sorted by column per row.
+
+#include "device_common.h"
+
+namespace tlt {
+
+namespace {
+
+constexpr int BT = 512;         // threads per workgroup
+constexpr int CPT = 8;          // columns per thread and chunk
+constexpr int CH = BT * CPT;    // columns per chunk
+constexpr int NBIN = 512;       // 9-bit digits
+constexpr int CAP = 96;         // candidates ranked in LDS per row
+constexpr int NDIG = 11;        // 7 digits of |w| (63 bits) + 4 of the column (31 bits)
+constexpr int KG_MAX = 8;
+
+// A row histograms (HIST) until its key range holds at most CAP entries,
+// collects (COLLECT) in the next pass, has its candidates ranked at the end
+// of that pass (RANK), and is then DONE.  Untruncated rows take ALL entries
+// in a single pass.
+enum { PH_HIST = 0, PH_COLLECT = 1, PH_DONE = 2, PH_ALL = 3, PH_RANK = 4 };
+
+struct KState {
+  uint64_t lo_w, hi_w;    // current key range (|w| bits)
+  uint32_t lo_j, hi_j;    // current range of 0x7fffffff - column
+  int phase, digit;
+  int above;              // entries known to rank above the range
+  int need;               // entries still to take from the range
+};
+
+__device__ __forceinline__ int digit_shift(int d) {
+  return d < 7 ? 54 - 9 * d : (d == 7 ? 22 : d == 8 ? 13 : d == 9 ? 4 : 0);
+}
+__device__ __forceinline__ int digit_bins(int d) { return d == 10 ? 16 : NBIN; }
+__device__ __forceinline__ int digit_of(int d, uint64_t kw, uint32_t kj) {
+  const int sh = digit_shift(d);
+  return d < 7 ? (int)((kw >> sh) & 511u) : (int)((kj >> sh) & (uint32_t)(digit_bins(d) - 1));
+}
+
+__device__ __forceinline__ uint64_t lanes_below() {
+  const int lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// base[key] += 1 for every active lane, one atomic per distinct key.
+__device__ __forceinline__ void agg_count(uint32_t *base, int key, bool act) {
+  uint64_t m = __ballot(act);
+  const int lane = threadIdx.x & 63;
+  while (m) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int k0 = __shfl(key, leader, 64);
+    const uint64_t same = __ballot(act && key == k0);
+    if (lane == leader) atomicAdd(&base[k0], (uint32_t)__popcll(same));
+    m &= ~same;
+  }
+}
+
+// Like agg_count, and returns each active lane's own slot (old value plus
+// its rank among the lanes of the same key).
+__device__ __forceinline__ int agg_slot(uint32_t *base, int key, bool act) {
+  uint64_t m = __ballot(act);
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lanes_below();
+  int slot = 0;
+  while (m) {
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int k0 = __shfl(key, leader, 64);
+    const uint64_t same = __ballot(act && key == k0);
+    uint32_t old = 0;
+    if (lane == leader) old = atomicAdd(&base[k0], (uint32_t)__popcll(same));
+    old = __shfl(old, leader, 64);
+    if (act && key == k0) slot = (int)old + __popcll(same & lt);
+    m &= ~same;
+  }
+  return slot;
+}
+
+__device__ __forceinline__ void store_value(void *val, int vdt, int64_t i, double v) {
+  switch (vdt) {
+    case 0: ((double *)val)[i] = v; break;
+    case 1: ((float *)val)[i] = (float)v; break;
+    case 2: ((uint16_t *)val)[i] = to_bf16((float)v); break;
+    default: ((uint16_t *)val)[i] = __builtin_bit_cast(uint16_t, (_Float16)(float)v); break;
+  }
+}
+
+struct Shared {
+  double *rn;          // [nr]
+  double2 *bs;         // [KG][nr] (basis, slope)
+  double *lv;          // [KG][BT] level values inside a chunk
+  double *cs;          // [KG][max_chunks] chunk scaling coefficients
+  uint32_t *hc;        // [KG][NBIN] histogram, or the candidates of a collecting row
+  uint32_t *outc;      // [KG] entries written in the collect pass
+  uint32_t *candc;     // [KG] candidates kept in the collect pass
+  KState *st;          // [KG]
+};
+
+// Candidate storage inside a row's histogram region (NBIN words).
+__device__ __forceinline__ uint64_t *cand_w(uint32_t *hc, int k) {
+  return reinterpret_cast<uint64_t *>(hc + (size_t)k * NBIN);
+}
+__device__ __forceinline__ double *cand_v(uint32_t *hc, int k) {
+  return reinterpret_cast<double *>(hc + (size_t)k * NBIN) + CAP;
+}
+__device__ __forceinline__ int32_t *cand_j(uint32_t *hc, int k) {
+  return reinterpret_cast<int32_t *>(hc + (size_t)k * NBIN + 4 * CAP);
+}
+
+// One generated coefficient w at column j of row (vertex, k).  Must be
+// called by every lane of the wave (inactive lanes pass valid = false);
+// k may differ between lanes.
+__device__ __forceinline__ void entry(const BuildArgs &a, const Shared &sh, const KState &s, int v,
+                                      int k, int j, double w, bool valid, int *bad) {
+  const int ph = valid ? s.phase : PH_DONE;
+  const uint64_t kw = (uint64_t)__double_as_longlong(w) & 0x7fffffffffffffffull;
+  const uint32_t kj = 0x7fffffffu - (uint32_t)j;
+  const bool in = kw >= s.lo_w && kw <= s.hi_w && kj >= s.lo_j && kj <= s.hi_j;
+  const bool up = kw > s.hi_w || (kw >= s.lo_w && kj > s.hi_j);
+  // histogram pass
+  const bool h = ph == PH_HIST && in;
+  agg_count(sh.hc, k * NBIN + (h ? digit_of(s.digit, kw, kj) : 0), h);
+  // collect pass: entries above the range are kept, the range's are ranked
+  const bool tk = ph == PH_COLLECT && up;
+  const int slot = agg_slot(sh.outc, k, tk);
+  if (tk) {
+    if (slot < s.above) {
+      const int64_t r = ((int64_t)v * a.K + a.kg0 + k) * a.n_keep + slot;
+      a.scol[r] = j;
+      a.sval[r] = w;
+    } else {
+      *bad = 1;
+    }
+  }
+  const bool cd = ph == PH_COLLECT && in;
+  const int cs = agg_slot(sh.candc, k, cd);
+  if (cd) {
+    if (cs < CAP) {
+      cand_w(sh.hc, k)[cs] = kw;
+      cand_v(sh.hc, k)[cs] = w;
+      cand_j(sh.hc, k)[cs] = j;
+    } else {
+      *bad = 1;
+    }
+  }
+  // untruncated rows: every coefficient at its own column
+  if (ph == PH_ALL) {
+    const int64_t r = ((int64_t)(a.o0 + v) * a.K + a.kg0 + k) * a.n_keep + j;
+    a.col[r] = j;
+    store_value(a.val, a.vdt, r, w);
+  }
+}
+
+// Haar levels l0+1, l0+2, ... over the n values buf[k*stride + 0..n) of
+// every row of the group (in place, sums to the front) until one value is
+// left, reporting each detail: detail p of level l of block `blk` sits at
+// column (n_cols >> l) + blk * (details per block at l) + p.
+__device__ __forceinline__ void lds_levels(const BuildArgs &a, const Shared &sh, int v, int KG,
+                                           double *buf, int stride, int n, int l0, int64_t blk,
+                                           double hsq, int *bad) {
+  const int t = threadIdx.x;
+  for (int l = l0 + 1; n > 1; ++l) {
+    const int half = n >> 1;
+    const int total = KG * half;
+    constexpr int MAXIT = KG_MAX * (CH / 16) / BT;  // items per thread at the widest level
+    double sv[MAXIT], dv[MAXIT];
+    int kk[MAXIT], pp[MAXIT];
+    bool ok[MAXIT];
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      const int item = it * BT + t;
+      ok[it] = item < total;
+      kk[it] = ok[it] ? item / half : 0;
+      pp[it] = ok[it] ? item % half : 0;
+      if (ok[it]) {
+        const double x0 = buf[kk[it] * stride + 2 * pp[it]];
+        const double x1 = buf[kk[it] * stride + 2 * pp[it] + 1];
+        dv[it] = (x0 - x1) * hsq;
+        sv[it] = (x0 + x1) * hsq;
+      } else {
+        dv[it] = 0.0;
+        sv[it] = 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+      if (it * BT < total) {  // uniform
+        if (ok[it]) buf[kk[it] * stride + pp[it]] = sv[it];
+        const int j = (int)((a.n_cols >> l) + blk * half + pp[it]);
+        const KState s = sh.st[kk[it]];
+        entry(a, sh, s, v, kk[it], j, dv[it], ok[it], bad);
+      }
+    }
+    __syncthreads();
+    n = half;
+  }
+}
+
+}  // namespace
+
+// grid: nv vertices (one workgroup each).  KG = number of k of this launch.
+template <int KG>
+__global__ __launch_bounds__(BT) void k_build_select(BuildArgs a) {
+#pragma clang fp contract(off)
+  extern __shared__ __align__(16) unsigned char smem[];
+  Shared sh;
+  {
+    unsigned char *p = smem;
+    sh.st = reinterpret_cast<KState *>(p);
+    p += sizeof(KState) * KG_MAX;
+    sh.outc = reinterpret_cast<uint32_t *>(p);
+    p += sizeof(uint32_t) * KG_MAX;
+    sh.candc = reinterpret_cast<uint32_t *>(p);
+    p += sizeof(uint32_t) * KG_MAX;
+    p = smem + ((p - smem + 15) / 16) * 16;
+    sh.hc = reinterpret_cast<uint32_t *>(p);
+    p += sizeof(uint32_t) * NBIN * KG;
+    sh.lv = reinterpret_cast<double *>(p);
+    p += sizeof(double) * BT * KG;
+    sh.cs = reinterpret_cast<double *>(p);
+    p += sizeof(double) * ((a.max_chunks * KG + 1) / 2 * 2);  // keeps bs 16-byte aligned
+    sh.bs = reinterpret_cast<double2 *>(p);
+    p += sizeof(double2) * a.nr * KG;
+    sh.rn = reinterpret_cast<double *>(p);
+  }
+  const int t = threadIdx.x;
+  const int v = blockIdx.x;        // vertex of this launch's range
+  const int o = a.o0 + v;          // Morton position of the output vertex
+  const int nr = a.nr;
+  const int N = a.N;
+  const bool haar = a.haar != 0;
+  const double hsq = a.hsq;
+  int bad = 0;
+
+  for (int i = t; i < nr; i += BT) sh.rn[i] = a.rn[i];
+  for (int i = t; i < nr * KG; i += BT) {
+    const int k = a.kg0 + i / nr, m = i % nr;
+    sh.bs[i] = double2{a.basis[(size_t)k * nr + m], a.slope[(size_t)k * nr + m]};
+  }
+  if (t < KG) {
+    KState s;
+    s.lo_w = 0;
+    s.hi_w = 0x7fffffffffffffffull;
+    s.lo_j = 0;
+    s.hi_j = 0x7fffffffu;
+    s.phase = a.all ? PH_ALL : PH_HIST;
+    s.digit = 0;
+    s.above = 0;
+    s.need = 0;
+    sh.st[t] = s;
+  }
+  const double xo = a.pos[3 * (size_t)o], yo = a.pos[3 * (size_t)o + 1], zo = a.pos[3 * (size_t)o + 2];
+  const int chw = a.n_cols < CH ? a.n_cols : CH;            // columns per chunk
+  const int n_chunks = (a.n_cols + chw - 1) / chw;
+  int lc = 0;                                                // Haar levels inside a chunk
+  while ((1 << lc) < chw) ++lc;
+  __syncthreads();
+
+  for (int pass = 0; pass <= NDIG + 1; ++pass) {
+    // prepare the pass; stop when every row is done
+    bool any = false;
+    for (int k = 0; k < KG; ++k) any |= sh.st[k].phase != PH_DONE;
+    if (!any) break;
+    for (int i = t; i < KG * NBIN; i += BT) {
+      if (sh.st[i / NBIN].phase == PH_HIST) sh.hc[i] = 0u;
+    }
+    if (t < KG) {
+      sh.outc[t] = 0u;
+      sh.candc[t] = 0u;
+    }
+    __syncthreads();
+
+    for (int c = 0; c < n_chunks; ++c) {
+      const int c0 = c * chw;
+      // this thread's CPT columns: distance, node and offset
+      int node[CPT];
+      double dr[CPT];
+      bool live[CPT];   // a column of the row (plain form) / a vertex (Haar)
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int i = c0 + t * CPT + q;
+        live[q] = (t * CPT + q < chw) && i < N;
+        node[q] = 0;
+        dr[q] = 0.0;
+        if (live[q]) {
+          const double dx = xo - a.pos[3 * (size_t)i];
+          const double dy = yo - a.pos[3 * (size_t)i + 1];
+          const double dz = zo - a.pos[3 * (size_t)i + 2];
+          const double r = sqrt(dx * dx + dy * dy + dz * dz);
+          int m;
+          if (r >= sh.rn[nr - 1]) {
+            m = nr - 1;
+          } else if (r <= 0.0) {
+            m = 0;
+          } else {
+            m = (int)((nr - 1) * sqrt(r / sh.rn[nr - 1]));
+            if (m > nr - 2) m = nr - 2;
+            if (m < 0) m = 0;
+            while (m > 0 && r < sh.rn[m]) --m;
+            while (m < nr - 2 && r >= sh.rn[m + 1]) ++m;
+          }
+          node[q] = m;
+          dr[q] = r - sh.rn[m];
+        }
+      }
+      const bool tin = t * CPT < chw;   // thread holds columns of this chunk
+      for (int k = 0; k < KG; ++k) {
+        const KState s = sh.st[k];
+        if (s.phase == PH_DONE) continue;  // uniform
+        double x[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          x[q] = 0.0;
+          if (live[q]) {
+            const int m = node[q];
+            const double2 b = sh.bs[k * nr + m];
+            x[q] = (m == nr - 1) ? sh.bs[k * nr + nr - 1].x : b.y * dr[q] + b.x;
+          }
+        }
+        if (haar) {
+          // levels 1..3 in registers (chw >= 8)
+          double s1[4], s2[2];
+#pragma unroll
+          for (int p = 0; p < 4; ++p) {
+            const double d = (x[2 * p] - x[2 * p + 1]) * hsq;
+            s1[p] = (x[2 * p] + x[2 * p + 1]) * hsq;
+            entry(a, sh, s, v, k, (a.n_cols >> 1) + (c0 >> 1) + 4 * t + p, d, tin, &bad);
+          }
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const double d = (s1[2 * p] - s1[2 * p + 1]) * hsq;
+            s2[p] = (s1[2 * p] + s1[2 * p + 1]) * hsq;
+            entry(a, sh, s, v, k, (a.n_cols >> 2) + (c0 >> 2) + 2 * t + p, d, tin, &bad);
+          }
+          {
+            const double d = (s2[0] - s2[1]) * hsq;
+            const double s3 = (s2[0] + s2[1]) * hsq;
+            entry(a, sh, s, v, k, (a.n_cols >> 3) + (c0 >> 3) + t, d, tin, &bad);
+            if (tin) sh.lv[k * BT + t] = s3;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < CPT; ++q) {
+            const int i = c0 + t * CPT + q;
+            entry(a, sh, s, v, k, i, x[q], (t * CPT + q < chw) && i < a.n_cols, &bad);
+          }
+        }
+      }
+      if (haar) {
+        __syncthreads();
+        // levels 4..lc over the chunk's chw/8 level-3 sums
+        lds_levels(a, sh, v, KG, sh.lv, BT, chw >> 3, 3, c, hsq, &bad);
+        if (t < KG) sh.cs[t * a.max_chunks + c] = sh.lv[t * BT];
+      }
+      __syncthreads();
+    }
+    if (haar) {
+      // coarse levels over the chunk sums, then the scaling coefficient
+      if (n_chunks > 1) lds_levels(a, sh, v, KG, sh.cs, a.max_chunks, n_chunks, lc, 0, hsq, &bad);
+      const int k0 = t < KG ? t : 0;
+      const KState s0 = sh.st[k0];
+      entry(a, sh, s0, v, k0, 0, sh.cs[k0 * a.max_chunks], t < KG, &bad);
+      __syncthreads();
+    }
+
+    // close the pass
+    if (t < KG) {
+      KState s = sh.st[t];
+      if (s.phase == PH_HIST) {
+        const int nb = digit_bins(s.digit);
+        int acc = s.above, b = nb - 1;
+        for (; b > 0; --b) {
+          const int hb = (int)sh.hc[t * NBIN + b];
+          if (acc + hb >= a.n_keep) break;
+          acc += hb;
+        }
+        const int cnt = (int)sh.hc[t * NBIN + b];
+        if (acc + cnt < a.n_keep) bad = 1;  // fewer entries than n_keep in range
+        const int shf = digit_shift(s.digit);
+        if (s.digit < 7) {
+          s.lo_w = (s.lo_w & ~(511ull << shf)) | ((uint64_t)b << shf);
+          s.hi_w = s.lo_w | ((1ull << shf) - 1ull);
+        } else {
+          const uint32_t mk = (uint32_t)(nb - 1);
+          s.lo_j = (s.lo_j & ~(mk << shf)) | ((uint32_t)b << shf);
+          s.hi_j = s.lo_j | ((1u << shf) - 1u);
+        }
+        s.above = acc;
+        s.need = a.n_keep - acc;
+        if (cnt <= CAP) {
+          s.phase = PH_COLLECT;
+        } else if (s.digit + 1 >= NDIG) {
+          bad = 1;
+          s.phase = PH_DONE;
+        } else {
+          s.digit += 1;
+        }
+        sh.st[t] = s;
+      } else if (s.phase == PH_ALL) {
+        s.phase = PH_DONE;
+        sh.st[t] = s;
+      } else if (s.phase == PH_COLLECT) {
+        if ((int)sh.outc[t] != s.above || (int)sh.candc[t] < s.need) bad = 1;
+        s.phase = PH_RANK;
+        sh.st[t] = s;
+      }
+    }
+    __syncthreads();
+    // rank the candidates of the rows that collected in this pass and take
+    // the best `need`
+    for (int item = t; item < KG * CAP; item += BT) {
+      const int k = item / CAP, i = item % CAP;
+      const KState s = sh.st[k];
+      if (s.phase != PH_RANK) continue;
+      const int nc = min((int)sh.candc[k], CAP);
+      if (i >= nc) continue;
+      const uint64_t wi = cand_w(sh.hc, k)[i];
+      const int ji = cand_j(sh.hc, k)[i];
+      int rank = 0;
+      for (int u = 0; u < nc; ++u) {
+        const uint64_t wu = cand_w(sh.hc, k)[u];
+        rank += (wu > wi || (wu == wi && cand_j(sh.hc, k)[u] < ji)) ? 1 : 0;
+      }
+      if (rank < s.need) {
+        const int64_t r = ((int64_t)v * a.K + a.kg0 + k) * a.n_keep + s.above + rank;
+        a.scol[r] = ji;
+        a.sval[r] = cand_v(sh.hc, k)[i];
+      }
+    }
+    __syncthreads();
+    if (t < KG && sh.st[t].phase == PH_RANK) sh.st[t].phase = PH_DONE;
+    __syncthreads();
+  }
+  if (t < KG && sh.st[t].phase != PH_DONE) bad = 1;
+  if (bad) atomicOr(a.status, 1);
+}
+
+// Sort the kept entries of each row by column; store columns and values.
+template <int P>
+__global__ __launch_bounds__(256) void k_build_sort(BuildArgs a) {
+  __shared__ uint64_t key[P];
+  const int r = blockIdx.x;                       // row of this launch's range
+  const int64_t g = (int64_t)a.o0 * a.K + r;      // global row
+  const int n = (int)a.n_keep;
+  const int t = threadIdx.x;
+  for (int i = t; i < P; i += 256)
+    key[i] = i < n ? (((uint64_t)(uint32_t)a.scol[(int64_t)r * n + i] << 32) | (uint32_t)i) : ~0ull;
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = t; i < P / 2; i += 256) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t x = key[lo], y = key[hi];
+        if ((x > y) == asc) {
+          key[lo] = y;
+          key[hi] = x;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += 256) {
+    const uint64_t kk = key[i];
+    const int slot = (int)(kk & 0xffffffffu);
+    a.col[g * n + i] = (int32_t)(kk >> 32);
+    store_value(a.val, a.vdt, g * n + i, a.sval[(int64_t)r * n + slot]);
+    if (i > 0 && (key[i - 1] >> 32) >= (kk >> 32)) atomicOr(a.status, 2);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-dense tiles from the (column, value) rows: the union of the kept
+// columns of a block's rows as a bitmap, its size (count pass), then the
+// union ids and the values scattered into the matrix-instruction operand
+// order (fill pass).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void block_bitmap(const TileBuildArgs &a, int b, uint32_t *bm) {
+  const int t = threadIdx.x;
+  for (int w = t; w < a.n_words; w += blockDim.x) bm[w] = 0u;
+  __syncthreads();
+  const int v0 = b * a.V, v1 = min(a.N, v0 + a.V);
+  const int64_t e0 = (int64_t)v0 * a.K * a.n_keep, e1 = (int64_t)v1 * a.K * a.n_keep;
+  for (int64_t e = e0 + t; e < e1; e += blockDim.x) {
+    const int j = a.col[e];
+    atomicOr(&bm[j >> 5], 1u << (j & 31));
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_tile_count(TileBuildArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
+  __shared__ uint32_t total;
+  const int b = blockIdx.x;
+  if (threadIdx.x == 0) total = 0u;
+  block_bitmap(a, b, bm);
+  uint32_t c = 0;
+  for (int w = threadIdx.x; w < a.n_words; w += blockDim.x) c += (uint32_t)__popc(bm[w]);
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&total, c);
+  __syncthreads();
+  if (threadIdx.x == 0) a.count[b] = (int64_t)((total + a.kstep - 1) / a.kstep * a.kstep);
+}
+
+__global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *pref = bm + a.n_words;
+  __shared__ uint32_t tsum[256];
+  __shared__ uint32_t total;
+  const int b = blockIdx.x;
+  const int t = threadIdx.x;
+  block_bitmap(a, b, bm);
+  // exclusive prefix of the word popcounts: contiguous word ranges per thread
+  const int per = (a.n_words + 255) / 256;
+  const int w0 = min(a.n_words, t * per), w1 = min(a.n_words, w0 + per);
+  uint32_t s = 0;
+  for (int w = w0; w < w1; ++w) s += (uint32_t)__popc(bm[w]);
+  tsum[t] = s;
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int i = 0; i < 256; ++i) {
+      const uint32_t x = tsum[i];
+      tsum[i] = acc;
+      acc += x;
+    }
+    total = acc;
+  }
+  __syncthreads();
+  s = tsum[t];
+  for (int w = w0; w < w1; ++w) {
+    pref[w] = s;
+    s += (uint32_t)__popc(bm[w]);
+  }
+  __syncthreads();
+  const int64_t off = a.blk_off[b];
+  const int64_t nu = a.blk_off[b + 1] - off;
+  // union column ids (ascending), then the padding (column 0, zero values)
+  for (int w = w0; w < w1; ++w) {
+    uint32_t bits = bm[w];
+    uint32_t u = pref[w];
+    while (bits) {
+      const int bit = __ffs(bits) - 1;
+      a.ucol[off + u] = 32 * w + bit;
+      ++u;
+      bits &= bits - 1u;
+    }
+  }
+  for (int64_t u = total + t; u < nu; u += 256) a.ucol[off + u] = 0;
+  // values in operand order
+  const int R = a.V * a.K, MT = R / 16, ks = a.kstep, kpl = ks / 4;
+  const int v0 = b * a.V, v1 = min(a.N, v0 + a.V);
+  const int64_t e0 = (int64_t)v0 * a.K * a.n_keep, e1 = (int64_t)v1 * a.K * a.n_keep;
+  for (int64_t e = e0 + t; e < e1; e += 256) {
+    const int j = a.col[e];
+    const int row = (int)((e - e0) / a.n_keep);
+    const uint32_t word = bm[j >> 5];
+    const int u = (int)(pref[j >> 5] + (uint32_t)__popc(word & ((1u << (j & 31)) - 1u)));
+    const int st = u / ks, rem = u % ks;
+    const int lane = (rem / kpl) * 16 + (row & 15);
+    const int64_t w = off * R + (((int64_t)st * MT + row / 16) * 64 + lane) * kpl + rem % kpl;
+    if (a.esz == 4)
+      ((uint32_t *)a.tval)[w] = ((const uint32_t *)a.val)[e];
+    else
+      ((uint16_t *)a.tval)[w] = ((const uint16_t *)a.val)[e];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launches.
+// ---------------------------------------------------------------------------
+
+size_t build_select_lds(int KG, int nr, int max_chunks) {
+  size_t p = sizeof(KState) * KG_MAX + 2 * sizeof(uint32_t) * KG_MAX;
+  p = (p + 15) / 16 * 16;
+  p += sizeof(uint32_t) * NBIN * KG + sizeof(double) * BT * KG +
+       sizeof(double) * ((max_chunks * KG + 1) / 2 * 2) + sizeof(double2) * nr * KG + sizeof(double) * nr;
+  return p;
+}
+
+int build_chunk_columns() { return CH; }
+int build_max_group() { return KG_MAX; }
+
+hipError_t launch_build_select(const BuildArgs &a, int KG, hipStream_t st) {
+  if (KG < 1 || KG > KG_MAX || a.nv < 1) return hipErrorInvalidValue;
+  const size_t lds = build_select_lds(KG, a.nr, a.max_chunks);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  switch (KG) {
+#define CASE(n) \
+  case n: hipLaunchKernelGGL(k_build_select<n>, dim3(a.nv), dim3(BT), lds, st, a); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_build_sort(const BuildArgs &a, hipStream_t st) {
+  const int64_t rows = (int64_t)a.nv * a.K;
+  int P = 64;
+  while (P < a.n_keep) P <<= 1;
+  switch (P) {
+#define CASE(n) \
+  case n: hipLaunchKernelGGL(k_build_sort<n>, dim3((unsigned)rows), dim3(256), 0, st, a); break;
+    CASE(64) CASE(128) CASE(256) CASE(512) CASE(1024) CASE(2048) CASE(4096) CASE(8192)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int build_sort_max() { return 8192; }
+
+hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st) {
+  const size_t lds = sizeof(uint32_t) * (size_t)a.n_words;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_count, dim3(a.n_blocks), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st) {
+  const size_t lds = 2 * sizeof(uint32_t) * (size_t)a.n_words;
+  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tile_fill, dim3(a.n_blocks), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace tlt

@@ -167,13 +167,6 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
 // rounded to nearest even (16-bit types via float32).
 // ---------------------------------------------------------------------------
 
-__device__ inline uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // NaN
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
 __global__ void k_quantize(const double *__restrict__ src, void *__restrict__ dst, int vdt,
                            int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

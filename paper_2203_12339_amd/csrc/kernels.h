@@ -109,6 +109,56 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
                           void *dSH, double *dTheta, hipStream_t st);
 size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64);
 
+// Load-time transport build on the device: kernel rows, Haar transform and
+// exact top-n selection for vertices [o0, o0 + nv) and the k of one group.
+struct BuildArgs {
+  const double *pos;       // [N][3] Morton order
+  const double *rn;        // [nr]
+  const double *basis;     // [K][nr]
+  const double *slope;     // [K][nr] (b[m+1] - b[m]) / (r[m+1] - r[m])
+  int N, n_cols, K, nr, haar;
+  double hsq;              // 1/sqrt(2) as the host computes it
+  int64_t n_keep;
+  int o0, nv, kg0;
+  int all;                 // n_keep == n_cols: every coefficient, in order
+  int max_chunks;          // LDS rows of chunk sums
+  int32_t *scol;           // [nv*K][n_keep] unsorted kept columns
+  double *sval;            // [nv*K][n_keep]
+  int32_t *col;            // final rows [N*K][n_keep]
+  void *val;               // storage type vdt
+  int vdt;
+  int *status;             // nonzero after a failed internal check
+};
+size_t build_select_lds(int KG, int nr, int max_chunks);
+int build_chunk_columns();
+int build_max_group();
+int build_sort_max();
+hipError_t launch_build_select(const BuildArgs &a, int KG, hipStream_t st);
+hipError_t launch_build_sort(const BuildArgs &a, hipStream_t st);
+
+// Block-dense tiles from the device rows (count pass, then fill pass).  A
+// block holds V consecutive Morton vertices, i.e. R = V*K rows (o, k).  Its
+// columns are the sorted union U of the kept columns of those rows, padded
+// to a multiple of `kstep` (padding columns point at column 0 with zero
+// weights).  Values are stored densely over [U x R] in operand order: for
+// k-step s, m-tile t (16 rows), lane l and element i < kpl the value
+// W[row = 16t + l%16][u = s*kstep + kpl*(l/16) + i], where kpl = kstep/4.
+struct TileBuildArgs {
+  const int32_t *col;      // [N*K][n_keep] ascending
+  const void *val;         // storage values (esz bytes)
+  int esz;
+  int N, K, V;
+  int64_t n_keep;
+  int n_words;             // ceil(n_cols / 32)
+  int n_blocks, kstep;
+  int64_t *count;          // count pass: padded union size per block
+  const int64_t *blk_off;  // fill pass: [n_blocks+1]
+  int32_t *ucol;
+  void *tval;              // zero-initialised
+};
+hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st);
+hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st);
+
 // Storage conversion of float64 values to device storage type.
 hipError_t launch_quantize(const double *src, void *dst, int vdt, int64_t n, hipStream_t st);
 

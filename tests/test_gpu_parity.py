@@ -72,6 +72,44 @@ def test_render_matches_oracle(name, kw):
     r.close()
 
 
+@pytest.mark.parametrize("name,n_rows", [("batch64-bf16-40962", 64), ("large-f16-163842", 48)])
+def test_full_size_sampled_rows(name, n_rows):
+    """Full-size workload, launched as the benchmark launches it: kept sets,
+    radiance and (large) the adjoint on seeded sampled output vertices."""
+    from oracle import adjoint
+    w = synth.get(name)
+    say(f"[full] {name}: N={w.n_vertices} K={w.K} n_keep={w.n_keep} n_out={w.n_out}; device build")
+    r, L, th, B = _render(w, save=True)
+    o = oracle_scene(w)
+    ids = synth.sample_rows(w, n_rows)
+    inv = np.empty(w.n_vertices, dtype=np.int64)
+    inv[o.perm] = np.arange(w.n_vertices)
+    p_rows = inv[ids]
+    # kept sets of a few rows, exactly
+    few = p_rows[:4]
+    col, _ = r.read_rows((few[:, None] * w.K + np.arange(w.K)[None, :]).reshape(-1))
+    oc, _ = o.kept_lists(few)
+    assert np.array_equal(col, oc.transpose(1, 0, 2).reshape(len(few) * w.K, -1))
+    say(f"[full] {name}: kept sets of {len(few)} rows match; oracle on {n_rows} rows")
+    ref = o.render_rows(L, th, p_rows, block=16)
+    got = B[:, ids, :]
+    e = normwise(got, ref)
+    say(f"[full] {name}: normwise {e:.3e} elementwise {elementwise(got, ref):.3e}")
+    assert e <= TOL[w.storage], e
+    if w.n_cfg == 1:
+        rng = np.random.default_rng(11)
+        bb_rows = rng.standard_normal((w.n_out, n_rows, 3))
+        bb = np.zeros_like(B)
+        bb[:, ids, :] = bb_rows
+        dSH, dTh = r.render_backward(dev_tensor(bb, "f32"))
+        gL_ref, gT_ref = adjoint.grad(o, L, th, bb_rows, rows=p_rows, block=16)
+        for g, ref_g, what in ((dSH.cpu().numpy(), gL_ref, "lighting"), (dTh.cpu().numpy(), gT_ref, "material")):
+            err = np.abs(g - ref_g).max() / np.abs(ref_g).max()
+            say(f"[full] {name}: {what} gradient rel err {err:.3e}")
+            assert err <= TOL[w.storage], err
+    r.close()
+
+
 def test_untruncated_wavelet_equals_plain_fp64():
     """Eq. (8): with nothing truncated the Haar form equals the plain form."""
     w = synth.get("dense-f64-642")
@@ -91,6 +129,14 @@ def test_stored_rows_match_host_build_and_oracle():
     m_rows = np.arange(0, w.n_vertices, 61)
     rows = (m_rows[:, None] * w.K + np.arange(w.K)[None, :]).reshape(-1)
     col, val = r.read_rows(rows)
+    # the device build against the host build of the same rows
+    hc, hv = tlt.build_rows(r.scene, w.n_keep, w.wavelet, m_rows)
+    hc = hc.reshape(len(rows), -1)
+    hv = hv.reshape(len(rows), -1)
+    assert np.array_equal(col, hc)
+    same = np.mean(val == hv.astype(np.float32))
+    say(f"[rows] device vs host build: columns equal, {100 * same:.4f}% of values bit-equal")
+    np.testing.assert_array_max_ulp(val, hv.astype(np.float32), maxulp=1)
     oc, ov = o.kept_lists(m_rows)                     # [K, P, n]
     oc = oc.transpose(1, 0, 2).reshape(len(rows), -1)
     ov = ov.transpose(1, 0, 2).reshape(len(rows), -1)
