@@ -901,7 +901,7 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
                 "render_backward needs a render with TLT_SAVE_FOR_BACKWARD of the current inputs");
   if (!dB || !dSH || !dTheta) return fail(&c->err, TLT_E_ARG, "NULL gradient pointer");
   hipStream_t st = (hipStream_t)stream;
-  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->fp64);
+  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->Cs, c->fp64);
   if (c->adj_bytes < need) {
     dfree(c->adj);
     c->adj_bytes = 0;

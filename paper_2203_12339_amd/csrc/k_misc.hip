@@ -39,21 +39,43 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
 //
 //   gbar[k][c]  = sum_o dB[c](perm[o]) * V[k][o][c]
 //   X[c][lm]    = sum_o dB[c](perm[o]) * sum_k g[k][c] P[k][o][lm]
-// Stage 1: one thread per output value and vertex block (ADJ_VB vertices),
-// partial sums to scratch.  Stage 2: fixed-order sum over blocks in float64,
-// then thetabar = sum gbar dg and dSH from X.
+// Per-block partial sums to scratch, then a fixed-order sum over blocks in
+// float64, then thetabar = sum gbar dg and dSH from X.  The float64 path
+// uses one thread per output value and block (ADJ_VB vertices).
 // ---------------------------------------------------------------------------
 
-constexpr int ADJ_VB = 256;
+constexpr int ADJ_VB = 256;   // vertices per block of the float64 path
+constexpr int ADJ_SPLIT = 16; // first-stage groups of the block reduction
 
-static size_t adj_red_offset(size_t nblk, size_t nout, bool fp64) {
-  return (nblk * nout * (fp64 ? 8 : 4) + 255) / 256 * 256;
+// Vertices per block of the float32 path: enough blocks to fill the chip.
+static int adj_block_vertices(int N, bool fp64) {
+  if (fp64) return ADJ_VB;
+  int vb = 256;
+  while (vb > 32 && (N + vb - 1) / vb < 1024) vb >>= 1;
+  return vb;
 }
 
-size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64) {
-  const size_t nblk = (N + ADJ_VB - 1) / ADJ_VB;
+// Scratch layout: per-block partials [nblk][nout] (compute type), the
+// first-stage float64 sums [ADJ_SPLIT][nout], the final float64 sums [nout],
+// and (float32) the Morton-ordered upstream gradient [N][Cs].
+struct AdjLayout {
+  size_t part, stage1, red, y, total;
+};
+static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
+static AdjLayout adj_layout(int N, int K, int n_sh, int C, int Cs, bool fp64) {
+  const size_t nblk = (N + adj_block_vertices(N, fp64) - 1) / adj_block_vertices(N, fp64);
   const size_t nout = (size_t)K * C + (size_t)C * n_sh;
-  return adj_red_offset(nblk, nout, fp64) + nout * 8;
+  AdjLayout l;
+  l.part = 0;
+  l.stage1 = a256(nblk * nout * (fp64 ? 8 : 4));
+  l.red = l.stage1 + a256((size_t)ADJ_SPLIT * nout * 8);
+  l.y = l.red + a256(nout * 8);
+  l.total = l.y + (fp64 ? 0 : sizeof(float) * (size_t)N * Cs);
+  return l;
+}
+
+size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, int Cs, bool fp64) {
+  return adj_layout(N, K, n_sh, C, Cs, fp64).total;
 }
 
 template <typename CT>
@@ -88,13 +110,171 @@ __global__ __launch_bounds__(256) void k_adj_partial(
   part[(size_t)blockIdx.x * (n_g + n_x) + t] = acc;
 }
 
+// float32 storage: the same partial sums from three streaming kernels.
+//   k_adj_permute: Y[o][c] = dB[c](perm[o]) in Morton order (stride Cs);
+//   k_adj_gbar:    gbar partials, V and Y streamed as float4 rows;
+//   k_adj_x:       X partials as a matrix product on the matrix cores over
+//                  the contraction index kappa = (k, o):
+//                  X[c][lm] += sum_kappa (g[k][c] Y[o][c]) * P[k][o][lm],
+//                  v_mfma_f32_16x16x4f32 (exact float32 products, float32
+//                  accumulation), operands staged in LDS ADJ_SUB vertices at
+//                  a time with float4 loads; each 16x16 (c, lm) tile belongs
+//                  to one wave and is summed in LDS over the block.
+constexpr int ADJ_SUB = 32;
+
+__global__ __launch_bounds__(256) void k_adj_permute(const float *__restrict__ dB,
+                                                     const int32_t *__restrict__ perm, int N, int C,
+                                                     int Cs, float *__restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (int64_t)N * Cs) return;
+  const int o = (int)(i / Cs), c = (int)(i - (int64_t)o * Cs);
+  float y = 0.f;
+  if (c < C) {
+    const int q = c / 3, ch = c - 3 * q;
+    y = dB[((int64_t)q * N + perm[o]) * 3 + ch];
+  }
+  Y[i] = y;
+}
+
+// grid (nblk, K): block b, term k.  Thread = (row phase r, column quad).
+__global__ __launch_bounds__(256) void k_adj_gbar(const float *__restrict__ V,
+                                                  const float *__restrict__ Y, int Cs, int N, int C,
+                                                  int nout, int vb, float *__restrict__ part) {
+  __shared__ float4 red[256];
+  const int t = threadIdx.x;
+  const int b = blockIdx.x, k = blockIdx.y;
+  const int o0 = b * vb;
+  const int nv = min(vb, N - o0);
+  const int cq = Cs / 4;            // column quads (Cs is a multiple of 16)
+  const int R = 256 / cq;           // rows in flight per pass
+  const int q4 = t % cq, r = t / cq;
+  float4 acc = {0.f, 0.f, 0.f, 0.f};
+  if (r < R) {
+    const float4 *v4 = reinterpret_cast<const float4 *>(V + ((int64_t)k * N + o0) * Cs) + q4;
+    const float4 *y4 = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs) + q4;
+#pragma unroll 4
+    for (int ol = r; ol < nv; ol += R) {
+      const float4 v = v4[(int64_t)ol * cq];
+      const float4 y = y4[(int64_t)ol * cq];
+      acc.x = fmaf(v.x, y.x, acc.x);
+      acc.y = fmaf(v.y, y.y, acc.y);
+      acc.z = fmaf(v.z, y.z, acc.z);
+      acc.w = fmaf(v.w, y.w, acc.w);
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  if (t < cq) {
+    float4 s = red[t];
+    for (int rr = 1; rr < R; ++rr) {
+      const float4 x = red[rr * cq + t];
+      s.x += x.x;
+      s.y += x.y;
+      s.z += x.z;
+      s.w += x.w;
+    }
+    const float sv[4] = {s.x, s.y, s.z, s.w};
+    for (int u = 0; u < 4; ++u) {
+      const int c = 4 * t + u;
+      if (c < C) part[(size_t)b * nout + (size_t)k * C + c] = sv[u];
+    }
+  }
+}
+
+size_t adjoint_x_lds(int K, int n_sh, int C, int Cs, int Psh) {
+  return sizeof(float) * ((size_t)ADJ_SUB * Cs + (size_t)K * ADJ_SUB * Psh + (size_t)K * Cs +
+                          (size_t)C * n_sh);
+}
+
+__global__ __launch_bounds__(256) void k_adj_x(const float *__restrict__ Y, int Cs,
+                                               const float *__restrict__ P, int Psh,
+                                               const float *__restrict__ gcol, int N, int K,
+                                               int n_sh, int C, int nout, int vb,
+                                               float *__restrict__ part) {
+  extern __shared__ __align__(16) float adj_sm[];
+  float *Ys = adj_sm;                           // [ADJ_SUB][Cs]
+  float *Ps = Ys + (size_t)ADJ_SUB * Cs;        // [K][ADJ_SUB][Psh]
+  float *gl = Ps + (size_t)K * ADJ_SUB * Psh;   // [K][Cs]
+  float *X = gl + (size_t)K * Cs;               // [C][n_sh]
+  const int t = threadIdx.x;
+  const int b = blockIdx.x;
+  const int n_g = K * C;
+  const int wave = t >> 6, lane = t & 63;
+  const int mtc = (C + 15) / 16, ntl = (n_sh + 15) / 16;
+  for (int i = t; i < K * Cs; i += 256) gl[i] = (i % Cs) < C ? gcol[i] : 0.f;
+  for (int i = t; i < C * n_sh; i += 256) X[i] = 0.f;
+  const int yq = ADJ_SUB * Cs / 4, pq = ADJ_SUB * Psh / 4;  // float4 per sub-block
+  for (int sb = 0; sb < vb / ADJ_SUB; ++sb) {
+    const int o0 = b * vb + sb * ADJ_SUB;
+    const int nv = max(0, min(ADJ_SUB, N - o0));
+    __syncthreads();  // previous sub-block done with Ys and Ps
+    {
+      const float4 z = {0.f, 0.f, 0.f, 0.f};
+      const float4 *ysrc = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs);
+      for (int i = t; i < yq; i += 256)
+        reinterpret_cast<float4 *>(Ys)[i] = (i / (Cs / 4) < nv) ? ysrc[i] : z;
+      for (int i = t; i < K * pq; i += 256) {
+        const int k = i / pq, w = i - k * pq;
+        const float4 *psrc = reinterpret_cast<const float4 *>(P + ((int64_t)k * N + o0) * Psh);
+        reinterpret_cast<float4 *>(Ps)[i] = (w / (Psh / 4) < nv) ? psrc[w] : z;
+      }
+    }
+    __syncthreads();
+    for (int tile = wave; tile < mtc * ntl; tile += 4) {
+      const int mt = tile / ntl, nt = tile - mt * ntl;
+      const int c = mt * 16 + (lane & 15);
+      const int lm = nt * 16 + (lane & 15);
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 8
+      for (int s = 0; s < K * ADJ_SUB / 4; ++s) {
+        const int kap = s * 4 + (lane >> 4);
+        const int k = kap / ADJ_SUB, ol = kap - k * ADJ_SUB;
+        const float a = gl[k * Cs + c] * Ys[ol * Cs + c];
+        const float bv = lm < n_sh ? Ps[(k * ADJ_SUB + ol) * Psh + lm] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cc = mt * 16 + 4 * (lane >> 4) + v;
+        const int ll = nt * 16 + (lane & 15);
+        if (cc < C && ll < n_sh) X[cc * n_sh + ll] += acc[v];
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < C * n_sh; i += 256) part[(size_t)b * nout + n_g + i] = X[i];
+}
+
+// Sum of the per-block partials in a fixed order, in float64.  Stage 1:
+// grid (output chunks of 64, ADJ_SPLIT groups of blocks); lane = output,
+// wave w sums a contiguous quarter of the group's blocks, the quarters are
+// added in order.  Stage 2: the ADJ_SPLIT group sums, in order.
 template <typename CT>
 __global__ __launch_bounds__(256) void k_adj_reduce(const CT *__restrict__ part, int nblk, int nout,
-                                                    double *__restrict__ out) {
+                                                    double *__restrict__ stage1) {
+  __shared__ double q4[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const int g = blockIdx.y;
+  const int g0 = (int)((int64_t)nblk * g / ADJ_SPLIT), g1 = (int)((int64_t)nblk * (g + 1) / ADJ_SPLIT);
+  const int b0 = g0 + (int)((int64_t)(g1 - g0) * w / 4), b1 = g0 + (int)((int64_t)(g1 - g0) * (w + 1) / 4);
+  double s = 0.0;
+  if (t < nout) {
+#pragma unroll 4
+    for (int bb = b0; bb < b1; ++bb) s += (double)part[(size_t)bb * nout + t];
+  }
+  q4[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && t < nout)
+    stage1[(size_t)g * nout + t] = ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
+}
+
+__global__ __launch_bounds__(256) void k_adj_reduce2(const double *__restrict__ stage1, int nout,
+                                                     double *__restrict__ out) {
   const int t = blockIdx.x * 256 + threadIdx.x;
   if (t >= nout) return;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += (double)part[(size_t)b * nout + t];
+  for (int g = 0; g < ADJ_SPLIT; ++g) s += stage1[(size_t)g * nout + t];
   out[t] = s;
 }
 
@@ -136,29 +316,43 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
                           int n_sh, Cols cols, bool fp64, void *partial, size_t partial_bytes,
                           void *dSH, double *dTheta, hipStream_t st) {
   const int C = cols.C;
-  const int nblk = (N + ADJ_VB - 1) / ADJ_VB;
+  const int vb = adj_block_vertices(N, fp64);
+  const int nblk = (N + vb - 1) / vb;
   const int nout = K * C + C * n_sh;
-  if (partial_bytes < adjoint_partial_bytes(N, K, n_sh, C, fp64)) return hipErrorInvalidValue;
-  double *red = (double *)((char *)partial + adj_red_offset(nblk, nout, fp64));
-  const dim3 g1(nblk, (nout + 255) / 256);
+  const AdjLayout l = adj_layout(N, K, n_sh, C, Cs, fp64);
+  if (partial_bytes < l.total) return hipErrorInvalidValue;
+  double *stage1 = (double *)((char *)partial + l.stage1);
+  double *red = (double *)((char *)partial + l.red);
   const int n_fin = cols.n_mat * 9 + cols.n_light * n_sh * 3;
+  const dim3 gr((nout + 63) / 64, ADJ_SPLIT);
   if (fp64) {
+    const dim3 g1(nblk, (nout + 255) / 256);
     hipLaunchKernelGGL(k_adj_partial<double>, g1, dim3(256), 0, st, (const double *)dB,
                        (const double *)V, Cs, (const double *)P, Psh, (const double *)gcol, perm,
                        N, K, n_sh, C, (double *)partial);
-    hipLaunchKernelGGL(k_adj_reduce<double>, dim3((nout + 255) / 256), dim3(256), 0, st,
-                       (const double *)partial, nblk, nout, red);
+    hipLaunchKernelGGL(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, nblk,
+                       nout, stage1);
+  } else {
+    const size_t lds = adjoint_x_lds(K, n_sh, C, Cs, Psh);
+    if (lds > 160 * 1024 || Cs % 16 != 0 || Cs > 1024 || Psh % 4 != 0) return hipErrorInvalidValue;
+    float *Y = (float *)((char *)partial + l.y);
+    const int64_t ny = (int64_t)N * Cs;
+    hipLaunchKernelGGL(k_adj_permute, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st,
+                       (const float *)dB, perm, N, C, Cs, Y);
+    hipLaunchKernelGGL(k_adj_gbar, dim3(nblk, K), dim3(256), 0, st, (const float *)V, Y, Cs, N, C,
+                       nout, vb, (float *)partial);
+    hipLaunchKernelGGL(k_adj_x, dim3(nblk), dim3(256), lds, st, Y, Cs, (const float *)P, Psh,
+                       (const float *)gcol, N, K, n_sh, C, nout, vb, (float *)partial);
+    hipLaunchKernelGGL(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, nblk,
+                       nout, stage1);
+  }
+  hipLaunchKernelGGL(k_adj_reduce2, dim3((nout + 255) / 256), dim3(256), 0, st, stage1, nout, red);
+  if (fp64)
     hipLaunchKernelGGL(k_adj_out<double>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
                        K, n_sh, cols, (double *)dSH, dTheta);
-  } else {
-    hipLaunchKernelGGL(k_adj_partial<float>, g1, dim3(256), 0, st, (const float *)dB,
-                       (const float *)V, Cs, (const float *)P, Psh, (const float *)gcol, perm, N,
-                       K, n_sh, C, (float *)partial);
-    hipLaunchKernelGGL(k_adj_reduce<float>, dim3((nout + 255) / 256), dim3(256), 0, st,
-                       (const float *)partial, nblk, nout, red);
+  else
     hipLaunchKernelGGL(k_adj_out<float>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
                        K, n_sh, cols, (float *)dSH, dTheta);
-  }
   return hipGetLastError();
 }
 

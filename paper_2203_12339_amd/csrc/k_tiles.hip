@@ -41,8 +41,9 @@ template <> struct TileKind<0> {
   static __device__ __forceinline__ f32x4 mma(AFrag a, BFrag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ AFrag load_a(const void *p, int64_t frag_elem) {
-    return ((const float *)p)[frag_elem];
+  static constexpr int VSZ = 4;  // bytes per stored value
+  static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) { hi = x; lo = 0; }
 };
@@ -54,9 +55,9 @@ template <> struct TileKind<1> {
   static __device__ __forceinline__ f32x4 mma(AFrag a, BFrag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ AFrag load_a(const void *p, int64_t frag_elem) {
-    const uint4 u = *(const uint4 *)((const uint16_t *)p + frag_elem);
-    return __builtin_bit_cast(AFrag, u);
+  static constexpr int VSZ = 2;
+  static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) {
     hi = (__bf16)x;
@@ -71,9 +72,9 @@ template <> struct TileKind<2> {
   static __device__ __forceinline__ f32x4 mma(AFrag a, BFrag b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
-  static __device__ __forceinline__ AFrag load_a(const void *p, int64_t frag_elem) {
-    const uint4 u = *(const uint4 *)((const uint16_t *)p + frag_elem);
-    return __builtin_bit_cast(AFrag, u);
+  static constexpr int VSZ = 2;
+  static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) {
     hi = (_Float16)x;
@@ -92,7 +93,13 @@ template <> struct TileKind<2> {
 // matrix work regardless of the staging.
 constexpr int TILE_LDS = 64 * 1024;  // staging budget per workgroup
 
-template <int KIND, int MTW, int NT, int PD, int IPT>
+// CGS: float32 tiles stage each (step, lane group) row of B with this
+// compile-time stride (>= the group's real columns), so the per-step LDS
+// offsets are immediates.
+// CSC: k-steps per staged chunk, a compile-time multiple of PD, so the
+// matrix work of a chunk is straight-line code and the load counters can
+// be waited on exactly.
+template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC>
 __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   typedef TileKind<KIND> TK;
   typedef typename TK::BElem BElem;
@@ -119,7 +126,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   const int cg = min(NT * 16, a.C - cbase);  // real columns of this group
   const int64_t u0 = a.blk_off[b];
   const int n_steps = (int)((a.blk_off[b + 1] - u0) / KS);
-  const int CS = a.kc;  // k-steps per staged chunk (a multiple of PD)
+  constexpr int CS = CSC;
   const int32_t *__restrict__ ucol = a.ucol + u0;
   const float *__restrict__ ehat = (const float *)a.ehat;
   const int64_t vbase = u0 * a.R;
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     it_eoff[it] = sl * KS + KPL * lg;
     it_col[it] = cbase + n;
     if constexpr (KIND == 0)
-      it_lds[it] = (sl * 4 + lg) * cg + n;
+      it_lds[it] = (sl * 4 + lg) * CGS + n;
     else
       it_lds[it] = ((sl * NT + n / 16) * H * 64 + lg * 16 + (n % 16)) * KPL;
   }
@@ -208,14 +215,35 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
 
-  // W fragments for step s of this wave's m-tiles (clamped past the end)
-  auto load_a = [&](int s, AFrag (&dst)[MTW]) {
-    const int ss = min(s, n_steps - 1);
+  // W fragments for step s of this wave's m-tiles, through a buffer
+  // resource over the block's values: the step is a scalar offset, the lane
+  // a fixed vector offset, and steps past the block's end read zeros
+  // without touching memory (the descriptor's bound).
+  const int step_bytes = MT * 64 * KPL * TK::VSZ;
+  const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)((const char *)a.val + vbase * TK::VSZ), (short)0, n_steps * step_bytes, 0x00020000);
+  int loff[MTW];
 #pragma unroll
-    for (int m = 0; m < MTW; ++m) {
-      const int t = wm * MTW + m;
-      dst[m] = TK::load_a(a.val, vbase + ((int64_t)(ss * MT + t) * 64 + lane) * KPL);
-    }
+  for (int m = 0; m < MTW; ++m) loff[m] = ((wm * MTW + m) * 64 + lane) * KPL * TK::VSZ;
+  auto load_a = [&](int s, AFrag (&dst)[MTW]) {
+#pragma unroll
+    for (int m = 0; m < MTW; ++m) dst[m] = TK::frag(wrs, loff[m], s * step_bytes);
+  };
+  // B fragments of step sl of the staged chunk (unconditional LDS reads)
+  auto read_b = [&](int sl, BFrag (&dst)[NT][H]) {
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        if constexpr (KIND == 0) {
+          const int n = nt * 16 + (lane & 15);
+          const float v = stage[((size_t)sl * 4 + (lane >> 4)) * CGS + min(n, cg - 1)];
+          dst[nt][h] = n < cg ? v : 0.f;
+        } else {
+          dst[nt][h] = *reinterpret_cast<const BFrag *>(
+              stage + ((size_t)((sl * NT + nt) * H + h) * 64 + lane) * KPL);
+        }
+      }
   };
   AFrag ring[PD][MTW];
 #pragma unroll
@@ -229,28 +257,46 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     const int nxt = s0 + CS;
     const int ns_next = min(CS, n_steps - nxt);
     if (ns_next > 0) gather(nxt, ns_next);
-    for (int g0 = 0; g0 < ns; g0 += PD) {
+    // Groups of PD steps: a group runs whole or not at all, so the W ring
+    // stays in step and the load counters can be waited on exactly; steps
+    // of the last group past the chunk's end multiply zero B fragments, and
+    // their W loads fall past the block's end and read zeros.
 #pragma unroll
-      for (int p = 0; p < PD; ++p) {
-        const int sl = g0 + p;
-        if (sl < ns) {
+    for (int g0 = 0; g0 < CS; g0 += PD) {
+      if (g0 < ns) {
+        float bg[KIND == 0 ? PD : 1];
+        if constexpr (KIND == 0) {
+          const int n = lane & 15;
+          const float *sp = stage + (size_t)g0 * 4 * CGS + (lane >> 4) * CGS + min(n, cg - 1);
 #pragma unroll
-          for (int nt = 0; nt < NT; ++nt) {
+          for (int p = 0; p < PD; ++p) bg[p] = sp[p * 4 * CGS];
 #pragma unroll
-            for (int h = 0; h < H; ++h) {
-              BFrag bf;
-              if constexpr (KIND == 0) {
-                const int n = nt * 16 + (lane & 15);
-                bf = (n < cg) ? stage[((size_t)sl * 4 + (lane >> 4)) * cg + n] : 0.f;
-              } else {
-                bf = *reinterpret_cast<const BFrag *>(
-                    stage + ((size_t)((sl * NT + nt) * H + h) * 64 + lane) * KPL);
-              }
+          for (int p = 0; p < PD; ++p) bg[p] = (n < cg && g0 + p < ns) ? bg[p] : 0.f;
+        }
 #pragma unroll
-              for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf, acc[m][nt]);
+        for (int p = 0; p < PD; ++p) {
+          const int sl = g0 + p;
+          BFrag bf[NT][H];
+          if constexpr (KIND == 0) {
+            bf[0][0] = bg[p];
+          } else {
+            read_b(min(sl, ns - 1), bf);
+            if (sl >= ns) {
+#pragma unroll
+              for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int h = 0; h < H; ++h) bf[nt][h] = BFrag{};
             }
           }
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+              for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
           load_a(s0 + sl + PD, ring[p]);  // refill this slot PD steps ahead
+          // keep the refill right behind its step (no regrouping of loads)
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
     }
@@ -339,7 +385,24 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   }
 }
 
-template <int KIND, int MTW, int NT, int PD, int IPT>
+template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC>
+static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
+  const int threads = (a.R / 16 / MTW) * 64;
+  a.kc = CSC;
+  a.wn = 1;
+  const bool reg_epi = a.K == 4 || a.K == 8 || a.K == 16;
+  size_t stage = std::max((size_t)CSC * per_step,
+                          reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
+  stage = (stage + 15) / 16 * 16;
+  a.uc_offset = (int)stage;
+  const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
+  hipLaunchKernelGGL((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC>), dim3(hw), dim3(threads), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int KIND, int MTW, int NT, int PD, int IPT, int CGS = 16>
 static hipError_t tiles_go(TileArgs a, int nt_total, hipStream_t st) {
   typedef TileKind<KIND> TK;
   const int MT = a.R / 16;
@@ -348,25 +411,25 @@ static hipError_t tiles_go(TileArgs a, int nt_total, hipStream_t st) {
   const int cmax = std::min(a.C, NT * 16);  // real columns of the widest group
   const int qw = KIND == 0 ? 1 : 4;
   const int items_per_step = 4 * ((cmax + qw - 1) / qw);
-  const size_t per_step = KIND == 0 ? (size_t)4 * cmax * sizeof(float)
+  if (KIND == 0 && cmax > CGS) return hipErrorInvalidValue;
+  const size_t per_step = KIND == 0 ? (size_t)4 * CGS * sizeof(float)
                                     : (size_t)NT * TK::H * 64 * TK::KPL * sizeof(typename TK::BElem);
   int cs = std::min<int>((int)(TILE_LDS / per_step), IPT * threads / items_per_step);
   if (a.kc > 0) cs = std::min(cs, a.kc);  // caller override (tuning)
-  cs = std::max(PD, cs / PD * PD);
-  if ((size_t)cs * items_per_step > (size_t)IPT * threads) return hipErrorInvalidValue;
-  a.kc = cs;
-  a.wn = 1;
-  const bool reg_epi = a.K == 4 || a.K == 8 || a.K == 16;
-  size_t stage = std::max((size_t)cs * per_step,
-                          reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
-  stage = (stage + 15) / 16 * 16;
-  a.uc_offset = (int)stage;
-  const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (cs < PD || (size_t)PD * items_per_step > (size_t)IPT * threads) return hipErrorInvalidValue;
   a.n_groups = (nt_total + NT - 1) / NT;
-  const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
-  hipLaunchKernelGGL((k_tiles<KIND, MTW, NT, PD, IPT>), dim3(hw), dim3(threads), lds, st, a);
-  return hipGetLastError();
+  // the largest compiled chunk length that fits
+  if constexpr (KIND == 0) {
+    if (cs >= 256) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 256>(a, per_step, st);
+    if (cs >= 128) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 128>(a, per_step, st);
+    if (cs >= 64) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 64>(a, per_step, st);
+    if (cs >= 32) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 32>(a, per_step, st);
+    return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 16>(a, per_step, st);
+  } else {
+    if (cs >= 16) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 16>(a, per_step, st);
+    if (cs >= 8) return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 8>(a, per_step, st);
+    return tiles_launch<KIND, MTW, NT, PD, IPT, CGS, 4>(a, per_step, st);
+  }
 }
 
 // Shapes: float32 tiles keep one m-tile per wave, one 16-column tile per
@@ -380,7 +443,10 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
   const int MT = a.R / 16;
   const int ntw = nt < 3 ? nt : 3;
   if constexpr (KIND == 0) {
-    return tiles_go<KIND, 1, 1, 16, 8>(a, nt, st);
+    const int cmax = a.C < 16 ? a.C : 16;
+    if (cmax <= 4) return tiles_go<KIND, 1, 1, 16, 8, 4>(a, nt, st);
+    if (cmax <= 8) return tiles_go<KIND, 1, 1, 16, 8, 8>(a, nt, st);
+    return tiles_go<KIND, 1, 1, 16, 8, 16>(a, nt, st);
   } else {
     if (MT == 8) {
       if (ntw == 1) return tiles_go<KIND, 2, 1, 4, 1>(a, nt, st);

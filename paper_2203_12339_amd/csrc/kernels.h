@@ -107,7 +107,7 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
                           const void *gcol, const double *dg64, const int32_t *perm, int N, int K,
                           int n_sh, Cols cols, bool fp64, void *partial, size_t partial_bytes,
                           void *dSH, double *dTheta, hipStream_t st);
-size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64);
+size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, int Cs, bool fp64);
 
 // Load-time transport build on the device: kernel rows, Haar transform and
 // exact top-n selection for vertices [o0, o0 + nv) and the k of one group.
