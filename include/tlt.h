@@ -149,8 +149,10 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  * Layout.  The rows are always kept as (column, value) pairs (the plain
  * form).  Unless layout is ROWS or the storage is F64, the library also
  * re-encodes them as block-dense tiles: V Morton-consecutive vertices
- * (V*K rows, 64..128) share the sorted union of their kept columns and are
- * stored densely over it (zeros where a row did not keep a column), in the
+ * (V*K rows: 48..128, a multiple of 16; tile_vertices, or by default
+ * 48..64 rows for F32 storage and up to 128 for 16-bit storage) share the
+ * sorted union of their kept columns and are stored densely over it
+ * (zeros where a row did not keep a column), in the
  * operand order of the 16x16 matrix instructions.  Both layouts hold the
  * same kept coefficients; render uses the tiles unless TLT_PLAIN_ROWS.
  * The library keeps its own device copies until tlt_destroy or the next
@@ -250,16 +252,19 @@ tlt_status tlt_set_tile(tlt_ctx *ctx, int columns_per_lane);
 int tlt_get_tile(const tlt_ctx *ctx);
 
 /*
- * Per-stage GPU timing.  While enabled, render and render_backward record a
- * pair of HIP events on their stream around each stage: 0 = material
- * weights g_k (Step 3), 1 = irradiance and its Haar transform (Step 1),
- * 2 = wavelet transport with K-term fusion (Steps 2 and 4), 3 = adjoint
- * reductions, 4 = material-only combine.  tlt_profile_enable(ctx, 1)
- * clears the totals; tlt_profile_read waits for the recorded events and
- * returns the summed elapsed milliseconds and the number of launches of a
- * stage.  Do not enable during HIP graph capture.
+ * Per-stage GPU timing.  While enabled, render and render_backward time
+ * each stage with a pair of HIP events written by the stage's own kernel
+ * dispatches (on their stream): 0 = material weights g_k (Step 3),
+ * 1 = irradiance and its Haar transform (Step 1), 2 = wavelet transport
+ * with K-term fusion (Steps 2 and 4), 3 = adjoint reductions,
+ * 4 = material-only combine.  mode 1 waits for pending events, clears the
+ * totals and enables; mode 0 pauses and mode 2 resumes without waiting or
+ * clearing (to time a sample of the renders of a running sequence).
+ * tlt_profile_read waits for the recorded events and returns the summed
+ * elapsed milliseconds and the number of timed launches of a stage.
+ * TLT_E_ARG for another mode.  Do not enable during HIP graph capture.
  */
-tlt_status tlt_profile_enable(tlt_ctx *ctx, int enable);
+tlt_status tlt_profile_enable(tlt_ctx *ctx, int mode);
 tlt_status tlt_profile_read(tlt_ctx *ctx, int stage, double *total_ms, int64_t *launches);
 
 /* Library version string (static storage). */

@@ -20,6 +20,13 @@
 
 using namespace tlt;
 
+namespace tlt {
+StageEvents &stage_events() {
+  static thread_local StageEvents ev;
+  return ev;
+}
+}  // namespace tlt
+
 struct tlt_ctx {
   int device = 0;
   std::string err;
@@ -169,6 +176,14 @@ void free_all(tlt_ctx *c) {
   c->n_light = c->n_mat = 0;
 }
 
+// Rows of Ehat per irradiance workgroup: 256, or 64 for Haar transforms
+// whose 256-row chunks would give too few workgroups to fill the chip.
+int prep_rows(const tlt_ctx *c, int Cs) {
+  int r = std::min(c->n_rows, 256);
+  if (c->wavelet == TLT_WAVELET_HAAR && (c->n_rows / 256) * (Cs / 16) < 512) r = std::min(c->n_rows, 64);
+  return r;
+}
+
 // (Re)allocates every buffer whose size depends on the column count.
 tlt_status ensure_columns(tlt_ctx *c) {
   const int n_out = std::max(c->n_light, c->n_mat);
@@ -188,7 +203,7 @@ tlt_status ensure_columns(tlt_ctx *c) {
   if (c->tiles && c->vdt != TLT_F32 &&
       (s = dalloc(c, &c->ehat2, 4 * (size_t)c->n_rows * c->Cs, "Ehat split")) != TLT_OK)
     return s;
-  const int ch_rows = std::min(c->n_rows, 256);
+  const int ch_rows = prep_rows(c, c->Cs);
   const int n_chunks = (c->n_rows + ch_rows - 1) / ch_rows;
   if ((s = dalloc(c, &c->partial, e * (size_t)n_chunks * c->Cs, "Haar partials")) != TLT_OK) return s;
   if ((s = dalloc(c, &c->gcol, e * (size_t)c->K * c->Cs, "column weights")) != TLT_OK) return s;
@@ -221,7 +236,7 @@ PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
   a.area = c->area;
   a.haar = c->wavelet == TLT_WAVELET_HAAR;
   a.n_rows = c->n_rows;
-  a.ch_rows = std::min(c->n_rows, 256);
+  a.ch_rows = prep_rows(c, Cs);
   a.n_chunks = (c->n_rows + a.ch_rows - 1) / a.ch_rows;
   return a;
 }
@@ -306,7 +321,16 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   return a;
 }
 
-int auto_tile_vertices(int K) {
+// Vertices per tile block.  float32 storage streams the most bytes per
+// kept coefficient, so it takes the smallest block (48..64 rows): nearby
+// vertices share more of their kept columns, fewer stored zeros (measured
+// ~10% fewer bytes at 48 than at 96 rows).  16-bit storage is bound by the
+// staging of Ehat as well, so it takes the largest block (up to 128 rows),
+// which shares each staged row among the most transport rows.
+int auto_tile_vertices(int K, int vdt) {
+  if (vdt == TLT_F32)
+    for (int R = 48; R <= 64; R += 16)
+      if (R % K == 0) return R / K;
   for (int V : {32, 16, 8, 4, 64})
     if (V * K >= 64 && V * K <= 128 && (V * K) % 16 == 0) return V;
   return 0;
@@ -367,7 +391,8 @@ out:
   return s;
 }
 
-// Stage timer: records an event pair around the launches of one stage.
+// Stage timer: hands an event pair to the launches of one stage (written by
+// the kernel dispatches themselves) and queues the pair for reading.
 struct StageTimer {
   tlt_ctx *c;
   int stage;
@@ -377,7 +402,7 @@ struct StageTimer {
     if (!c->prof) return;
     a = take();
     b = take();
-    if (a) (void)hipEventRecord(a, st);
+    if (a && b) stage_events() = StageEvents{a, b, 0};
   }
   hipEvent_t take() {
     if (!c->pool.empty()) {
@@ -390,9 +415,16 @@ struct StageTimer {
     return e;
   }
   ~StageTimer() {
-    if (!c->prof || !a || !b) return;
-    (void)hipEventRecord(b, st);
-    c->pending.push_back({stage, a, b});
+    if (!c->prof) return;
+    const int n = stage_events().launches;
+    stage_events() = StageEvents{};
+    if (!a || !b) return;
+    if (n > 0) {
+      c->pending.push_back({stage, a, b});
+    } else {  // nothing launched: the pair was never written
+      c->pool.push_back(a);
+      c->pool.push_back(b);
+    }
   }
 };
 
@@ -711,14 +743,14 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   tlt_status s;
   const size_t vsz = dtype_size(c->vdt);
   const size_t nnz = (size_t)n_rowsW * (size_t)d->n_keep;
-  const int tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K);
+  const int tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K, d->value_dtype);
   // (the tile build keeps two bitmaps of n_cols bits in LDS)
-  const bool tiles_ok = tV > 0 && tV * d->K >= 64 && tV * d->K <= 128 && (tV * d->K) % 16 == 0 &&
+  const bool tiles_ok = tV > 0 && tV * d->K >= 48 && tV * d->K <= 128 && (tV * d->K) % 16 == 0 &&
                         (size_t)8 * ((n_cols + 31) / 32) <= (size_t)150 * 1024;
   const bool want_tiles = !c->fp64 && d->layout != TLT_LAYOUT_ROWS && tiles_ok;
   if (d->layout == TLT_LAYOUT_TILES && (c->fp64 || !tiles_ok)) {
     s = fail(&c->err, TLT_E_ARG,
-             "tiles need non-F64 storage, 64 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
+             "tiles need non-F64 storage, 48 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
     goto fail_all;
   }
   if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
@@ -916,14 +948,17 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
   return TLT_OK;
 }
 
-tlt_status tlt_profile_enable(tlt_ctx *c, int enable) {
+tlt_status tlt_profile_enable(tlt_ctx *c, int mode) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
-  prof_drain(c);
-  for (int i = 0; i < 5; ++i) {
-    c->prof_ms[i] = 0.0;
-    c->prof_n[i] = 0;
+  if (mode < 0 || mode > 2) return fail(&c->err, TLT_E_ARG, "mode must be 0, 1 or 2");
+  if (mode == 1) {
+    prof_drain(c);
+    for (int i = 0; i < 5; ++i) {
+      c->prof_ms[i] = 0.0;
+      c->prof_n[i] = 0;
+    }
   }
-  c->prof = enable != 0;
+  c->prof = mode != 0;
   return TLT_OK;
 }
 

@@ -5,7 +5,23 @@
 #include <algorithm>
 #include <cstdint>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
+
+// Kernel launch that carries the profiled stage's timing events, if any.
+#define TLT_LAUNCH(KERNEL, GRID, BLOCK, LDS, STREAM, ...)                                  \
+  do {                                                                                      \
+    ::tlt::StageEvents &ev_ = ::tlt::stage_events();                                        \
+    if (ev_.stop) {                                                                         \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, ev_.start, ev_.stop, 0,       \
+                            __VA_ARGS__);                                                   \
+      ev_.start = nullptr;                                                                  \
+      ev_.launches += 1;                                                                    \
+    } else {                                                                                \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);                    \
+    }                                                                                       \
+  } while (0)
 
 namespace tlt {
 

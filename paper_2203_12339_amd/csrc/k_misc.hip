@@ -26,10 +26,10 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
   const int64_t n = (int64_t)N * C;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   if (fp64)
-    hipLaunchKernelGGL(k_combine<double>, dim3(blocks), dim3(256), 0, st, (const double *)V, Cs,
+    TLT_LAUNCH(k_combine<double>, dim3(blocks), dim3(256), 0, st, (const double *)V, Cs,
                        (const double *)gcol, K, N, C, perm, (double *)B);
   else
-    hipLaunchKernelGGL(k_combine<float>, dim3(blocks), dim3(256), 0, st, (const float *)V, Cs,
+    TLT_LAUNCH(k_combine<float>, dim3(blocks), dim3(256), 0, st, (const float *)V, Cs,
                        (const float *)gcol, K, N, C, perm, (float *)B);
   return hipGetLastError();
 }
@@ -327,31 +327,31 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
   const dim3 gr((nout + 63) / 64, ADJ_SPLIT);
   if (fp64) {
     const dim3 g1(nblk, (nout + 255) / 256);
-    hipLaunchKernelGGL(k_adj_partial<double>, g1, dim3(256), 0, st, (const double *)dB,
+    TLT_LAUNCH(k_adj_partial<double>, g1, dim3(256), 0, st, (const double *)dB,
                        (const double *)V, Cs, (const double *)P, Psh, (const double *)gcol, perm,
                        N, K, n_sh, C, (double *)partial);
-    hipLaunchKernelGGL(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, nblk,
+    TLT_LAUNCH(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, nblk,
                        nout, stage1);
   } else {
     const size_t lds = adjoint_x_lds(K, n_sh, C, Cs, Psh);
     if (lds > 160 * 1024 || Cs % 16 != 0 || Cs > 1024 || Psh % 4 != 0) return hipErrorInvalidValue;
     float *Y = (float *)((char *)partial + l.y);
     const int64_t ny = (int64_t)N * Cs;
-    hipLaunchKernelGGL(k_adj_permute, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st,
+    TLT_LAUNCH(k_adj_permute, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st,
                        (const float *)dB, perm, N, C, Cs, Y);
-    hipLaunchKernelGGL(k_adj_gbar, dim3(nblk, K), dim3(256), 0, st, (const float *)V, Y, Cs, N, C,
+    TLT_LAUNCH(k_adj_gbar, dim3(nblk, K), dim3(256), 0, st, (const float *)V, Y, Cs, N, C,
                        nout, vb, (float *)partial);
-    hipLaunchKernelGGL(k_adj_x, dim3(nblk), dim3(256), lds, st, Y, Cs, (const float *)P, Psh,
+    TLT_LAUNCH(k_adj_x, dim3(nblk), dim3(256), lds, st, Y, Cs, (const float *)P, Psh,
                        (const float *)gcol, N, K, n_sh, C, nout, vb, (float *)partial);
-    hipLaunchKernelGGL(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, nblk,
+    TLT_LAUNCH(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, nblk,
                        nout, stage1);
   }
-  hipLaunchKernelGGL(k_adj_reduce2, dim3((nout + 255) / 256), dim3(256), 0, st, stage1, nout, red);
+  TLT_LAUNCH(k_adj_reduce2, dim3((nout + 255) / 256), dim3(256), 0, st, stage1, nout, red);
   if (fp64)
-    hipLaunchKernelGGL(k_adj_out<double>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
+    TLT_LAUNCH(k_adj_out<double>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
                        K, n_sh, cols, (double *)dSH, dTheta);
   else
-    hipLaunchKernelGGL(k_adj_out<float>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
+    TLT_LAUNCH(k_adj_out<float>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
                        K, n_sh, cols, (float *)dSH, dTheta);
   return hipGetLastError();
 }

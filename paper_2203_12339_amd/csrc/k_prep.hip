@@ -346,12 +346,12 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t st) {
   const size_t lds = prep_lds_bytes(a);
   if (a.fp64) {
     if (a.tdt != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_prep<double, double>), dim3(blocks), dim3(256), lds, st, a);
+    TLT_LAUNCH((k_prep<double, double>), dim3(blocks), dim3(256), lds, st, a);
   } else {
     switch (a.tdt) {
-      case 1: hipLaunchKernelGGL((k_prep<float, float>), dim3(blocks), dim3(256), lds, st, a); break;
-      case 2: hipLaunchKernelGGL((k_prep<bf16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
-      case 3: hipLaunchKernelGGL((k_prep<f16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      case 1: TLT_LAUNCH((k_prep<float, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      case 2: TLT_LAUNCH((k_prep<bf16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
+      case 3: TLT_LAUNCH((k_prep<f16s, float>), dim3(blocks), dim3(256), lds, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
@@ -360,11 +360,11 @@ hipError_t launch_prep(const PrepArgs &a, hipStream_t st) {
   if (a.n_tl_blocks > 0 && a.haar && a.n_chunks > 1) {
     const size_t lds2 = (size_t)a.n_chunks * 3 / 2 * (a.fp64 ? 8 : 4);
     if (a.fp64)
-      hipLaunchKernelGGL((k_haar_top<double>), dim3(a.Cs), dim3(256), lds2, st,
+      TLT_LAUNCH((k_haar_top<double>), dim3(a.Cs), dim3(256), lds2, st,
                          (const double *)a.partial, a.n_chunks, a.Cs, (double *)a.ehat,
                          (uint32_t *)nullptr, 0);
     else
-      hipLaunchKernelGGL((k_haar_top<float>), dim3(a.Cs), dim3(256), lds2, st,
+      TLT_LAUNCH((k_haar_top<float>), dim3(a.Cs), dim3(256), lds2, st,
                          (const float *)a.partial, a.n_chunks, a.Cs, (float *)a.ehat,
                          (uint32_t *)a.ehat2, a.split);
     e = hipGetLastError();

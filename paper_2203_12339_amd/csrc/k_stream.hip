@@ -165,7 +165,7 @@ constexpr int stream_epl(int cpl) { return cpl <= 4 ? 8 : (cpl <= 8 ? 4 : (cpl <
 template <typename VT, typename CT, int CPL, int EPL, bool NT>
 static hipError_t stream_go(const StreamArgs &a, int n_chunks, hipStream_t st) {
   const int hw = ((a.n_logical_blocks + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_stream<VT, CT, CPL, EPL, NT>), dim3(hw, n_chunks), dim3(256), 0, st, a);
+  TLT_LAUNCH((k_stream<VT, CT, CPL, EPL, NT>), dim3(hw, n_chunks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -398,7 +398,7 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
-  hipLaunchKernelGGL((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC>), dim3(hw), dim3(threads), lds, st, a);
+  TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC>), dim3(hw), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 
@@ -462,7 +462,7 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
 int tile_kstep(int vdt) { return vdt == 1 ? 4 : 32; }
 
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st) {
-  if (a.R % 16 != 0 || a.R < 64 || a.R > 128 || a.n_blocks <= 0) return hipErrorInvalidValue;
+  if (a.R % 16 != 0 || a.R < 48 || a.R > 128 || a.n_blocks <= 0) return hipErrorInvalidValue;
   switch (vdt) {
     case 1: return tiles_kind<0>(a, st);
     case 2: return tiles_kind<1>(a, st);

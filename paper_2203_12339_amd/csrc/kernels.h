@@ -11,6 +11,16 @@ namespace tlt {
 struct bf16s { uint16_t u; };
 struct f16s { uint16_t u; };
 
+// Timing of the stage being profiled (thread-local, set by the host around
+// the launches of one stage): the first launch of the stage writes `start`
+// and every launch writes `stop`, as part of the kernel dispatch itself, so
+// no marker packets sit between the kernels.
+struct StageEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int launches = 0;
+};
+StageEvents &stage_events();
+
 // Column mapping of a launch: column c = 3*q + ch of output set q uses
 // lighting (n_light > 1 ? q : 0) and material (n_mat > 1 ? q : 0).
 struct Cols {

@@ -345,7 +345,15 @@ class Renderer:
     STAGES = {"weights": 0, "irradiance": 1, "transport": 2, "adjoint": 3, "combine": 4}
 
     def profile(self, enable=True):
+        """Clear the stage totals and enable timing (True), or pause it."""
         _check(_profile_enable(self._h, 1 if enable else 0), self._h)
+
+    def profile_pause(self):
+        _check(_profile_enable(self._h, 0), self._h)
+
+    def profile_resume(self):
+        """Resume timing without waiting or clearing the totals."""
+        _check(_profile_enable(self._h, 2), self._h)
 
     def profile_read(self, stage):
         ms = ctypes.c_double()
