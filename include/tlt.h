@@ -252,6 +252,27 @@ tlt_status tlt_set_tile(tlt_ctx *ctx, int columns_per_lane);
 int tlt_get_tile(const tlt_ctx *ctx);
 
 /*
+ * Launch tuning of a context (kept across load_transport; 0 restores the
+ * built-in choice).  Keys:
+ *   TLT_TUNE_TILE_CHUNK          largest number of k-steps of a tile block
+ *                                whose irradiance rows are staged at once
+ *   TLT_TUNE_STREAM_WAVES_PER_CU waves per compute unit of the row kernel
+ *   TLT_TUNE_STREAM_EPL          entries per lane and step of the row kernel
+ *                                for narrow launches: 4, 8 or 16
+ *   TLT_TUNE_STREAM_NT           1 = non-temporal loads of the rows
+ * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
+ * key or a value out of range.  Results do not depend on the tuning beyond
+ * float32 summation order.
+ */
+enum {
+  TLT_TUNE_TILE_CHUNK = 1,
+  TLT_TUNE_STREAM_WAVES_PER_CU = 2,
+  TLT_TUNE_STREAM_EPL = 3,
+  TLT_TUNE_STREAM_NT = 4
+};
+tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
+
+/*
  * Per-stage GPU timing.  While enabled, render and render_backward time
  * each stage with a pair of HIP events written by the stage's own kernel
  * dispatches (on their stream): 0 = material weights g_k (Step 3),

@@ -78,6 +78,9 @@ struct tlt_ctx {
   void *t_val = nullptr;
   size_t t_val_bytes = 0;
 
+  // tuning (tlt_set_tuning; 0 = built-in choice)
+  int tune_tile_chunk = 0, tune_waves_per_cu = 0, tune_stream_epl = 0, tune_stream_nt = 0;
+
   // transport partition: n_waves equal row ranges; split vertices cleared
   int n_waves = 0;
   int32_t *zero_v = nullptr;
@@ -244,8 +247,7 @@ PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
 // Equal row ranges per wave; vertices straddling two ranges are listed so
 // the prep launch can clear their outputs before the atomic completion.
 tlt_status ensure_partition(tlt_ctx *c) {
-  const char *e = std::getenv("TLT_WAVES_PER_CU");
-  const int wpc = (e && std::atoi(e) > 0) ? std::atoi(e) : 32;
+  const int wpc = c->tune_waves_per_cu > 0 ? c->tune_waves_per_cu : 32;
   const int nw = stream_waves(c->N, c->K, wpc);
   if (nw == c->n_waves && (c->zero_v || c->n_zero == 0)) return TLT_OK;
   dfree(c->zero_v);
@@ -287,10 +289,8 @@ StreamArgs stream_args(tlt_ctx *c, const void *ehat, int Cs, int C, const void *
   a.vs_stride = vs_stride;
   a.R = (int64_t)c->N * c->K;
   a.n_waves = c->n_waves;
-  const char *e = std::getenv("TLT_STREAM_EPL");
-  a.epl = e ? std::atoi(e) : 0;
-  const char *nt = std::getenv("TLT_STREAM_NT");
-  a.nt = nt ? std::atoi(nt) : 0;
+  a.epl = c->tune_stream_epl;
+  a.nt = c->tune_stream_nt;
   return a;
 }
 
@@ -316,8 +316,7 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   a.B = B;
   a.vsave = vsave;
   a.vs_stride = vs_stride;
-  const char *e = std::getenv("TLT_TILE_KC");
-  a.kc = e ? std::atoi(e) : 0;
+  a.kc = c->tune_tile_chunk;
   return a;
 }
 
@@ -898,6 +897,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     a.partial = c->partial;
     a.ehat2 = c->ehat2;
     a.split = c->vdt == TLT_BF16 ? 1 : 2;
+    if (!use_tiles && (s = ensure_partition(c)) != TLT_OK) return s;
     if (c->n_zero > 0 && !use_tiles) {
       a.B = B;
       a.zero_v = c->zero_v;
@@ -915,6 +915,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
                                        save ? c->V : nullptr, c->Cs),
                              c->vdt, st));
       } else {
+        if ((s = ensure_partition(c)) != TLT_OK) return s;
         StreamArgs sa = stream_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs);
         HIPC(c, launch_stream(sa, c->vdt, c->fp64, c->cpl, st));
       }
@@ -945,6 +946,26 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
   StageTimer t(c, 3, st);
   HIPC(c, launch_adjoint(dB, c->V, c->Cs, c->P, c->Psh, c->gcol, c->dg64, c->perm, c->N, c->K,
                          c->n_sh, cols, c->fp64, c->adj, c->adj_bytes, dSH, dTheta, st));
+  return TLT_OK;
+}
+
+tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (value < 0) return fail(&c->err, TLT_E_ARG, "tuning values are >= 0 (0 = built-in choice)");
+  switch (key) {
+    case TLT_TUNE_TILE_CHUNK: c->tune_tile_chunk = value; break;
+    case TLT_TUNE_STREAM_WAVES_PER_CU: c->tune_waves_per_cu = value; break;
+    case TLT_TUNE_STREAM_EPL:
+      if (value != 0 && value != 4 && value != 8 && value != 16)
+        return fail(&c->err, TLT_E_ARG, "entries per lane must be 4, 8 or 16");
+      c->tune_stream_epl = value;
+      break;
+    case TLT_TUNE_STREAM_NT:
+      if (value > 1) return fail(&c->err, TLT_E_ARG, "non-temporal flag must be 0 or 1");
+      c->tune_stream_nt = value;
+      break;
+    default: return fail(&c->err, TLT_E_ARG, "unknown tuning key");
+  }
   return TLT_OK;
 }
 

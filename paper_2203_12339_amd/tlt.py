@@ -28,6 +28,10 @@ STATUS = {0: "TLT_OK", 1: "TLT_W_MATERIAL_OUT_OF_RANGE", -1: "TLT_E_ARG", -2: "T
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+# torch first: it brings its own HIP runtime, and the library must bind to
+# that same runtime (two runtimes in one process do not share devices).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 _p = ctypes.c_void_p
@@ -84,6 +88,7 @@ _read_state = _sig("tlt_read_state", ctypes.c_int, _p, ctypes.c_int, _p,
 _set_tile = _sig("tlt_set_tile", ctypes.c_int, _p, ctypes.c_int)
 _get_tile = _sig("tlt_get_tile", ctypes.c_int, _p)
 _version = _sig("tlt_version", ctypes.c_char_p)
+_set_tuning = _sig("tlt_set_tuning", ctypes.c_int, _p, ctypes.c_int32, ctypes.c_int32)
 _profile_enable = _sig("tlt_profile_enable", ctypes.c_int, _p, ctypes.c_int)
 _profile_read = _sig("tlt_profile_read", ctypes.c_int, _p, ctypes.c_int,
                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64))
@@ -94,7 +99,11 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
-            "tlt_profile_enable", "tlt_profile_read"]
+            "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read"]
+
+TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
+TUNING_KEYS = {"tile_chunk": TUNE_TILE_CHUNK, "stream_waves_per_cu": TUNE_STREAM_WAVES_PER_CU,
+               "stream_epl": TUNE_STREAM_EPL, "stream_nt": TUNE_STREAM_NT}
 
 
 class TltError(RuntimeError):
@@ -361,6 +370,10 @@ class Renderer:
         _check(_profile_read(self._h, self.STAGES.get(stage, stage), ctypes.byref(ms),
                              ctypes.byref(n)), self._h)
         return ms.value, n.value
+
+    def set_tuning(self, key, value: int):
+        """key: a TUNING_KEYS name or TUNE_* code; value 0 = built-in choice."""
+        _check(_set_tuning(self._h, TUNING_KEYS.get(key, key), int(value)), self._h)
 
     def set_tile(self, cpl: int):
         _check(_set_tile(self._h, int(cpl)), self._h)

@@ -17,11 +17,23 @@ def scene_for(w: synth.Workload, K=None):
 
 
 def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout="auto",
-                 tile_vertices=0) -> Renderer:
+                 tile_vertices=0, tuned=True) -> Renderer:
+    """A renderer with the workload's transport loaded.  With ``tuned`` (and
+    no explicit tile size) the autotuner's recorded shape for exactly this
+    workload is applied, if there is one."""
     sc = scene_for(w, K) if scene is None else scene
+    entry = None
+    if tuned and tile_vertices == 0 and layout != "rows" and K is None:
+        from .autotune import lookup
+        entry = lookup(w)
+        if entry is not None:
+            tile_vertices = entry["tile_vertices"]
     r = Renderer(device)
     r.load_transport(sc, w.n_keep, storage=w.storage, wavelet=w.wavelet, layout=layout,
                      tile_vertices=tile_vertices)
+    if entry is not None:
+        r.set_tuning("tile_chunk", entry["tile_chunk"])
     r.scene = sc
     r.workload = w
+    r.tuning = entry
     return r

@@ -272,3 +272,24 @@ def test_error_paths_on_device():
         r.set_tile(5)
     assert ei.value.status == -1
     r.close()
+
+
+def test_autotune_sweeps_shapes_that_all_match_oracle():
+    """The autotuner's sweep on a small workload, and every swept tile block
+    size rendering the oracle's result."""
+    from paper_2203_12339_amd import autotune
+    w = synth.get("haar-f32-10242").with_(subdiv=4, n_light=2, n_cfg=2)
+    say("[autotune] haar-f32 subdiv 4")
+    e = autotune.tune(w, steps=4, log=say)
+    assert e["tile_vertices"] in autotune.vertex_candidates(w.K)
+    assert len(e["sweep"]) == len(autotune.vertex_candidates(w.K)) * len(autotune.chunk_candidates("f32"))
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ref = oracle_scene(w).render(L, th)
+    for V in autotune.vertex_candidates(w.K):
+        r = renderer_for(w, tile_vertices=V)
+        for kc in autotune.chunk_candidates("f32"):
+            r.set_tuning("tile_chunk", kc)
+            _, _, _, B = _render(w, L, th, renderer=r)
+            assert normwise(B, ref) <= TOL["f32"], (V, kc)
+        r.close()

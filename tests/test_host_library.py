@@ -95,3 +95,19 @@ def test_host_error_paths():
     with pytest.raises(tlt.TltError):
         tlt.build_rows(sc, 4, "haar", [42])                    # row out of range
     assert "row out of range" in tlt._last_error(None).decode()
+
+
+def test_autotune_candidates_and_table():
+    """Every candidate tile shape is one the tile kernel accepts, and the
+    recorded table (if any) only names such shapes."""
+    from paper_2203_12339_amd import autotune
+    for K in (4, 6, 8, 12, 16):
+        for V in autotune.vertex_candidates(K):
+            assert (V * K) % 16 == 0 and 48 <= V * K <= 128
+    assert autotune.vertex_candidates(6) == [8, 16]
+    for key, e in autotune.load_table().items():
+        storage, K = key.split("/")[0], int(key.split("/")[1][1:])
+        assert storage in ("f32", "bf16", "f16")
+        assert e["tile_vertices"] in autotune.vertex_candidates(K)
+        assert e["tile_chunk"] in autotune.chunk_candidates(storage)
+        assert e["key"] == key
