@@ -754,7 +754,7 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   }
   if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->val, vsz * nnz, "transport values")) != TLT_OK) goto fail_all;
-  if ((s = dalloc(c, &c->T, dtype_size(c->tdt) * (size_t)N * c->n_sh, "transfer")) != TLT_OK) goto fail_all;
+  if ((s = dalloc(c, &c->T, dtype_size(c->tdt) * (size_t)N * c->n_sh + 64, "transfer")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->area, c->esz * N, "areas")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, (void **)&c->perm, sizeof(int32_t) * N, "perm")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, (void **)&c->rn, sizeof(double) * c->nr, "r nodes")) != TLT_OK) goto fail_all;

@@ -178,7 +178,13 @@ __device__ __forceinline__ void store_e(CT *ehat, uint32_t *ehat2, int split, si
 template <typename TT, typename CT>
 __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   typedef typename MfmaOut<CT>::V4 V4;
+  // LDS: x [TL_CH][TL_STRIDE] (E, then the Haar levels), Ts [ch_rows *
+  // n_sh] (the chunk's transfer rows, contiguous as in T), Ls [n_shp][16]
+  // (lighting columns of the tile), As [ch_rows] (areas)
   CT *x = reinterpret_cast<CT *>(smem);
+  TT *Ts = reinterpret_cast<TT *>(x + TL_CH * TL_STRIDE);   // storage type, as in T
+  CT *Ls = reinterpret_cast<CT *>(Ts + ((size_t)a.ch_rows * a.n_sh + 15) / 16 * 16);
+  CT *As = Ls + (size_t)a.n_shp * 16;
   const int chunk = t % a.n_chunks;
   const int ctile = t / a.n_chunks;
   const int c0 = ctile * 16;
@@ -192,33 +198,61 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   uint32_t *ehat2 = (uint32_t *)a.ehat2;
   CT *partial = (CT *)a.partial;
 
-  // lighting column of this lane (B operand column n = li)
-  const int c = c0 + li;
-  int sh_base = -1;
-  if (sh != nullptr && c < a.cols.C) {
-    const int q = c / 3, ch = c - 3 * q;
-    const int l = a.cols.n_light > 1 ? q : 0;
-    sh_base = (l * a.n_sh) * 3 + ch;
+  // Stage everything the chunk reads with one batch of loads.  The chunk's
+  // transfer rows are one contiguous range of T, read as 16-byte vectors
+  // through a buffer resource (reads past the end of T return zeros), all
+  // issued before any is used.
+  const int nr = max(0, min(a.ch_rows, a.N - i0));         // real vertices of the chunk
+  {
+    constexpr int TSZ = sizeof(TT), VEC = 16 / TSZ, VPT = 8;
+    const int nel = nr * a.n_sh;                            // elements of the chunk
+    const int nvec = (nel + VEC - 1) / VEC;
+    const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((const char *)T + (size_t)i0 * a.n_sh * TSZ), (short)0, nel * TSZ, 0x00020000);
+    for (int v0 = 0; v0 < nvec; v0 += 256 * VPT) {
+      uint4 buf[VPT];
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int v = v0 + u * 256 + threadIdx.x;
+        buf[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               trs, v < nvec ? v * 16 : nel * TSZ, 0, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < VPT; ++u) {
+        const int v = v0 + u * 256 + threadIdx.x;
+        if (v < nvec) reinterpret_cast<uint4 *>(Ts)[v] = buf[u];
+      }
+    }
+    for (int idx = threadIdx.x; idx < a.n_shp * 16; idx += 256) {
+      const int kc = idx >> 4, n = idx & 15, c = c0 + n;
+      CT b = 0;
+      if (kc < a.n_sh) {
+        if (sh == nullptr) {
+          b = (kc == c) ? CT(1) : CT(0);
+        } else if (c < a.cols.C) {
+          const int q = c / 3, ch = c - 3 * q;
+          const int l = a.cols.n_light > 1 ? q : 0;
+          b = sh[((size_t)l * a.n_sh + kc) * 3 + ch];
+        }
+      }
+      Ls[idx] = b;
+    }
+    for (int idx = threadIdx.x; idx < a.ch_rows; idx += 256) As[idx] = idx < nr ? area[i0 + idx] : CT(0);
   }
+  __syncthreads();
   if (64 * wave < a.ch_rows) {
     V4 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = V4{0, 0, 0, 0};
     for (int kk = 0; kk < a.n_shp; kk += 4) {
       const int kc = kk + lk;
-      CT b = 0;
-      if (kc < a.n_sh) {
-        if (sh == nullptr)
-          b = (kc == c) ? CT(1) : CT(0);
-        else if (sh_base >= 0)
-          b = sh[sh_base + kc * 3];
-      }
+      const CT b = Ls[kc * 16 + li];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int r = i0 + 64 * wave + 16 * u + li;
-        CT av = 0;
-        if (r < a.N && kc < a.n_sh && 64 * wave + 16 * u < a.ch_rows)
-          av = ld<TT, CT>(T, (int64_t)r * a.n_sh + kc);
+        const int lr = 64 * wave + 16 * u + li;
+        // rows past the last vertex (zero padding) and columns past n_sh
+        // were never staged: they contribute zeros
+        const CT av = (lr < nr && kc < a.n_sh) ? ld<TT, CT>(Ts, lr * a.n_sh + kc) : CT(0);
         acc[u] = mfma16(av, b, acc[u]);
       }
     }
@@ -227,9 +261,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int lr = 64 * wave + 16 * u + MfmaOut<CT>::row(lk, v);
-        const int r = i0 + lr;
-        const CT ar = (r < a.N) ? area[r] : CT(0);
-        if (lr < a.ch_rows) x[lr * TL_STRIDE + li] = acc[u][v] * ar;
+        if (lr < a.ch_rows) x[lr * TL_STRIDE + li] = acc[u][v] * As[lr];
       }
     }
   }
@@ -336,7 +368,9 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
 size_t prep_lds_bytes(const PrepArgs &a) {
   const size_t esz = a.fp64 ? 8 : 4;
   size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // material weights
-  s = std::max(s, (size_t)TL_CH * TL_STRIDE * esz);
+  if (a.n_tl_blocks > 0)
+    s = std::max(s, esz * ((size_t)TL_CH * TL_STRIDE + (size_t)a.n_shp * 16 + (size_t)a.ch_rows) +
+                        ((size_t)a.ch_rows * a.n_sh + 15) / 16 * 16 * (a.tdt == 0 ? 8 : a.tdt == 1 ? 4 : 2));
   return s;
 }
 
