@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", action="store_true",
                     help="use the (column, value) row kernel instead of the tiles")
+    ap.add_argument("--folded", action="store_true",
+                    help="relight through the folded lighting transport B = sum_k g_k P_k L")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -132,8 +134,11 @@ def main():
     r.set_material(tt)
     B = torch.empty((w.n_out, w.n_vertices, 3), dtype=ldt, device=dev)
     dB = torch.randn_like(B) if args.backward else None
+    if args.folded and (args.backward or args.plain):
+        print("--folded excludes --backward and --plain", file=sys.stderr)
+        sys.exit(2)
     flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0) | \
-        (tlt.PLAIN_ROWS if args.plain else 0)
+        (tlt.PLAIN_ROWS if args.plain else 0) | (tlt.FOLDED_LIGHTING if args.folded else 0)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -184,16 +189,24 @@ def main():
     esz = 8 if w.storage == "f64" else 4
     nnz = w.n_vertices * w.K * w.n_keep
     n_rows = w.n_pad if w.wavelet == "haar" else w.n_vertices
-    alg_bytes = nnz * (4 + vsz) + n_rows * C * esz + w.n_vertices * C * esz
+    if args.folded:
+        # P_k rows read once (Psh >= n_sh columns, as stored), B written once
+        psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
+        alg_bytes = w.K * w.n_vertices * psh * esz + w.n_vertices * C * esz
+        kernel, traffic = "k_folded", None
+        flops = 2.0 * w.K * w.n_vertices * w.n_sh * C
+    else:
+        alg_bytes = nnz * (4 + vsz) + n_rows * C * esz + w.n_vertices * C * esz
+        kernel = "k_stream" if args.plain else "k_tiles"
+        traffic = None if args.plain else stored_traffic(w.name, C)
+        flops = 2.0 * nnz * C
     avg_s = ms_tr / max(n_tr, 1) * 1e-3
     achieved = alg_bytes / avg_s / 1e9
-    traffic = stored_traffic(w.name, C)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "kernel": "k_stream" if args.plain else "k_tiles",
+                "traffic": traffic, "kernel": kernel,
                 "kernel_us": round(avg_s * 1e6, 2), "kernel_launches_timed": n_tr,
                 "algorithmic_bytes": alg_bytes}
-    flops = 2.0 * nnz * C
     ai = flops / alg_bytes
 
     # accuracy of this very output on a sample of rows + the CPU oracle time
@@ -229,7 +242,7 @@ def main():
             "n_vertices": w.n_vertices, "K": w.K, "n_keep": w.n_keep, "n_sh": w.n_sh,
             "storage": w.storage, "lightings": w.n_light, "materials": w.n_cfg,
             "columns": C, "backward": bool(args.backward), "tile": r.tile(),
-            "layout": "rows" if args.plain else "tiles",
+            "layout": "folded lighting" if args.folded else ("rows" if args.plain else "tiles"),
             "tile_shape": ({"tile_vertices": r.tuning["tile_vertices"], "tile_chunk": r.tuning["tile_chunk"],
                             "source": "autotuner table"} if getattr(r, "tuning", None) else "built-in"),
             "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),

@@ -56,7 +56,8 @@ enum { TLT_WAVELET_NONE = 0, TLT_WAVELET_HAAR = 1 };
 enum {
   TLT_SAVE_FOR_BACKWARD = 1, /* keep v_k[o,c] for render_backward */
   TLT_FORCE_FULL = 2,        /* recompute every stage, ignoring dirty flags */
-  TLT_PLAIN_ROWS = 4         /* use the (column, value) row kernel even when tiles exist */
+  TLT_PLAIN_ROWS = 4,        /* use the (column, value) row kernel even when tiles exist */
+  TLT_FOLDED_LIGHTING = 8    /* relight through P_k = W_k H (A o T): B = sum_k g_k P_k L */
 };
 enum { TLT_LAYOUT_AUTO = 0, TLT_LAYOUT_ROWS = 1, TLT_LAYOUT_TILES = 2 };
 
@@ -213,6 +214,11 @@ tlt_status set_lighting(tlt_ctx *ctx, int n_light, const void *sh_dev);
  * Recomputes only what changed since the last render (a material change
  * reruns Steps 3-4 of Sec. 4 only) unless TLT_FORCE_FULL.  With
  * TLT_SAVE_FOR_BACKWARD keeps v_k[o,c] for render_backward.
+ * TLT_FOLDED_LIGHTING renders through the lighting transport folded at load,
+ * P_k = W_k H (A o T) (the SH-lighting path of Eq. 14): B = sum_k g_k P_k L,
+ * equal to the wavelet transport of the same kept coefficients up to
+ * float32 rounding, reading K*N*Psh values instead of the transport
+ * (incompatible with TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS: TLT_E_ARG).
  * TLT_E_STATE before load_transport / set_material / set_lighting.
  */
 tlt_status render(tlt_ctx *ctx, void *B_dev, void *hip_stream, int flags);

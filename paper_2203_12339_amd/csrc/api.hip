@@ -67,6 +67,8 @@ struct tlt_ctx {
   double *g64 = nullptr, *dg64 = nullptr;
   void *adj = nullptr;
   size_t adj_bytes = 0;
+  void *fold = nullptr;   // folded lighting weights [K*Psh][Cs]
+  size_t fold_bytes = 0;
   bool v_valid = false;   // V holds v_k of the current lighting
   int n_chunks = 0, ch_rows = 0;
 
@@ -150,6 +152,8 @@ void free_columns(tlt_ctx *c) {
   dfree(c->dg64);
   dfree(c->adj);
   c->adj_bytes = 0;
+  dfree(c->fold);
+  c->fold_bytes = 0;
   c->C = c->Cs = c->n_out = 0;
   c->buf_nlight = c->buf_nmat = -1;
   c->v_valid = false;
@@ -862,8 +866,10 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (!B) return fail(&c->err, TLT_E_ARG, "B is NULL");
   if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
     return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
-  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS))
+  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING))
     return fail(&c->err, TLT_E_ARG, "unknown flags");
+  if ((flags & TLT_FOLDED_LIGHTING) && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS)))
+    return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING excludes TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS");
   hipStream_t st = (hipStream_t)stream;
   tlt_status s;
   if ((s = ensure_columns(c)) != TLT_OK) return s;
@@ -882,7 +888,25 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     a.dg64 = c->dg64;
     a.gcol = c->gcol;
   }
-  if (!relight && c->V) {
+  if (flags & TLT_FOLDED_LIGHTING) {
+    // g_k when the material changed, then the folded product
+    if (!c->have_P && (s = ensure_P(c, st)) != TLT_OK) return s;
+    if (do_gk) {
+      StageTimer t(c, 0, st);
+      HIPC(c, launch_prep(a, st));
+    }
+    const size_t need = folded_scratch_bytes(c->K, c->Psh, c->Cs, c->fp64);
+    if (c->fold_bytes < need) {
+      dfree(c->fold);
+      c->fold_bytes = 0;
+      if ((s = dalloc(c, &c->fold, need, "folded lighting weights")) != TLT_OK) return s;
+      c->fold_bytes = need;
+    }
+    StageTimer t(c, 2, st);
+    HIPC(c, launch_folded(c->P, c->Psh, c->n_sh, c->K, c->gcol, c->Cs, c->sh, cols, c->N, c->perm, B,
+                          c->fp64, c->fold, st));
+    c->v_valid = false;
+  } else if (!relight && c->V) {
     // material-only edit: reuse the saved per-term transport v_k
     if (do_gk) {
       StageTimer t(c, 0, st);

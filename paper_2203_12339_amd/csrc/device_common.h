@@ -94,6 +94,27 @@ template <int CPL> struct RowLoad<double, CPL> {
   }
 };
 
+// 16x16x4 matrix instruction in the compute type, and the row of result
+// element v held by lane group lk (lanes 16*lk .. 16*lk+15; the column is
+// lane % 16).  The f64 form lays its result out differently (measured on
+// gfx950 with known operands).
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename CT> struct MfmaOut;
+template <> struct MfmaOut<float> {
+  typedef f32x4 V4;
+  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
+};
+template <> struct MfmaOut<double> {
+  typedef f64x4 V4;
+  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
+};
+
 // Hardware workgroup b runs on XCD b % 8: remap so that each XCD gets a
 // contiguous range of logical blocks (neighbouring vertices share L2 lines).
 __device__ __forceinline__ int xcd_remap(int b, int n_logical) {

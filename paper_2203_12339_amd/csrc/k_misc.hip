@@ -35,6 +35,180 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
 }
 
 // ---------------------------------------------------------------------------
+// Folded lighting transport (Eq. 14, the SH lighting path): with
+// P_k = W_k H (A o T) (built at load, [K][N][Psh], Morton rows),
+//   B[o, c] = sum_k g_k[c] sum_lm P_k[o, lm] L[light(c)][lm][ch(c)],
+// one matrix product over the contraction index (k, lm):
+//   B[o, c] = sum_(k,lm) P[o, (k,lm)] Lg[(k,lm), c],  Lg = g_k[c] L[lm][c].
+// In exact arithmetic this equals the wavelet transport for the same kept
+// coefficients.  Workgroup: 64 rows (one 16-row tile per wave) x up to 64
+// columns (FOLD_CG); Lg of the column group is built in LDS; every wave
+// reads its P rows directly (one element per lane and step, all loads of a
+// term issued before its matrix work).
+// ---------------------------------------------------------------------------
+
+constexpr int FOLD_CG = 64;   // columns per workgroup
+
+// Lg[(k, lm)][c] = g_k[c] L[light(c)][lm][ch(c)] (zero past n_sh and C).
+template <typename CT>
+__global__ __launch_bounds__(256) void k_fold_weights(const CT *__restrict__ gcol, int Cs,
+                                                      const CT *__restrict__ sh, Cols cols, int K,
+                                                      int Psh, int n_sh, CT *__restrict__ Lg) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= K * Psh * Cs) return;
+  const int c = i % Cs, kl = i / Cs;
+  const int k = kl / Psh, lm = kl - k * Psh;
+  CT v = 0;
+  if (c < cols.C && lm < n_sh) {
+    const int q = c / 3, ch = c - 3 * q;
+    const int l = cols.n_light > 1 ? q : 0;
+    v = gcol[(size_t)k * Cs + c] * sh[((size_t)l * n_sh + lm) * 3 + ch];
+  }
+  Lg[i] = v;
+}
+
+// Each wave owns FOLD_RT 16-row tiles and FOLD_CG columns.  For each term k
+// it holds that term's operands of Lg in registers (read from the small,
+// cache-resident Lg) and streams the P_k rows of its tiles: all A operands of
+// a term (FOLD_RT x steps values per lane) are requested before the term's
+// matrix work.  No LDS, so many waves per compute unit hide the latency.
+// NTN real 16-column tiles, MS = Psh / 4 steps, RT tiles per wave: all
+// compile-time, so the loads of a term carry no branches (addresses are
+// clamped into range and values past the end are zeroed by selects) and
+// stay in flight together.
+template <typename CT, int NTN, int MS, int RT>
+__global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Psh, int K,
+                                                const CT *__restrict__ Lg, int Cs, int C, int N,
+                                                const int32_t *__restrict__ perm,
+                                                CT *__restrict__ B) {
+  typedef typename MfmaOut<CT>::V4 V4;
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int cg0 = blockIdx.y * FOLD_CG;
+  const int tile0 = (blockIdx.x * 4 + wave) * RT;       // first 16-row tile of the wave
+  V4 acc[RT][NTN];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int nt = 0; nt < NTN; ++nt) acc[r][nt] = V4{0, 0, 0, 0};
+  const CT *prow[RT];
+  bool rok[RT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+    const int o = (tile0 + r) * 16 + li;
+    rok[r] = o < N;
+    prow[r] = P + (int64_t)min(o, N - 1) * Psh;
+  }
+  int bcol[NTN];
+#pragma unroll
+  for (int nt = 0; nt < NTN; ++nt) bcol[nt] = min(cg0 + nt * 16 + li, Cs - 1);
+  for (int k = 0; k < K; ++k) {
+    const int64_t koff = (int64_t)k * N * Psh;
+    CT av[RT][MS];
+    CT bv[MS][NTN];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+      const int lm = 4 * s + lk;   // < Psh: MS * 4 == Psh
+#pragma unroll
+      for (int r = 0; r < RT; ++r) av[r][s] = prow[r][koff + lm];
+      const CT *lrow = Lg + (size_t)(k * Psh + lm) * Cs;
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt) bv[s][nt] = lrow[bcol[nt]];
+    }
+#pragma unroll
+    for (int s = 0; s < MS; ++s)
+#pragma unroll
+      for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int nt = 0; nt < NTN; ++nt)
+          acc[r][nt] = mfma16(rok[r] ? av[r][s] : CT(0), bv[s][nt], acc[r][nt]);
+  }
+#pragma unroll
+  for (int r = 0; r < RT; ++r) {
+#pragma unroll
+    for (int nt = 0; nt < NTN; ++nt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = (tile0 + r) * 16 + MfmaOut<CT>::row(lk, v);
+        const int c = cg0 + nt * 16 + li;
+        if (o < N && c < C) {
+          const int q = c / 3, ch = c - 3 * q;
+          B[((int64_t)q * N + perm[o]) * 3 + ch] = acc[r][nt][v];
+        }
+      }
+    }
+  }
+}
+
+template <typename CT, int NTN, int MS>
+static void folded_rt(dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh, int K, const CT *Lg,
+                      int Cs, int C, int N, const int32_t *perm, CT *B) {
+  // tiles per wave: the most that still leaves >= 512 workgroups
+  if ((tiles + 15) / 16 >= 512)
+    TLT_LAUNCH((k_folded<CT, NTN, MS, 4>), dim3((tiles + 15) / 16, gx.y), dim3(256), 0, st, P, Psh, K,
+               Lg, Cs, C, N, perm, B);
+  else if ((tiles + 7) / 8 >= 512)
+    TLT_LAUNCH((k_folded<CT, NTN, MS, 2>), dim3((tiles + 7) / 8, gx.y), dim3(256), 0, st, P, Psh, K,
+               Lg, Cs, C, N, perm, B);
+  else
+    TLT_LAUNCH((k_folded<CT, NTN, MS, 1>), dim3((tiles + 3) / 4, gx.y), dim3(256), 0, st, P, Psh, K,
+               Lg, Cs, C, N, perm, B);
+}
+
+template <typename CT, int NTN>
+static hipError_t folded_ms(dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh, int K,
+                            const CT *Lg, int Cs, int C, int N, const int32_t *perm, CT *B) {
+  switch (Psh / 4) {
+#define CASE(m) \
+  case m: folded_rt<CT, NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(7) CASE(8) CASE(9) CASE(12) CASE(16)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+template <typename CT>
+static hipError_t folded_go(int C, int Cs, dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh,
+                            int K, const CT *Lg, int N, const int32_t *perm, CT *B) {
+  // real column tiles of the widest group
+  const int ntn = (std::min(FOLD_CG, C) + 15) / 16;
+  switch (ntn) {
+    case 1: return folded_ms<CT, 1>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
+    case 2: return folded_ms<CT, 2>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
+    case 3: return folded_ms<CT, 3>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
+    default: return folded_ms<CT, 4>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
+  }
+}
+
+size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64) {
+  return (size_t)K * Psh * Cs * (fp64 ? 8 : 4);
+}
+
+hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
+                         const void *sh, Cols cols, int N, const int32_t *perm, void *B, bool fp64,
+                         void *scratch, hipStream_t st) {
+  if (Psh > 64 || Cs % 16 != 0) return hipErrorInvalidValue;
+  const int nw = K * Psh * Cs;
+  const int tiles = (N + 15) / 16;
+  const dim3 gx(1, (Cs + FOLD_CG - 1) / FOLD_CG);
+  hipError_t e;
+  if (fp64) {
+    TLT_LAUNCH(k_fold_weights<double>, dim3((nw + 255) / 256), dim3(256), 0, st,
+               (const double *)gcol, Cs, (const double *)sh, cols, K, Psh, n_sh, (double *)scratch);
+    e = folded_go<double>(cols.C, Cs, gx, tiles, st, (const double *)P, Psh, K,
+                          (const double *)scratch, N, perm, (double *)B);
+  } else {
+    TLT_LAUNCH(k_fold_weights<float>, dim3((nw + 255) / 256), dim3(256), 0, st,
+               (const float *)gcol, Cs, (const float *)sh, cols, K, Psh, n_sh, (float *)scratch);
+    e = folded_go<float>(cols.C, Cs, gx, tiles, st, (const float *)P, Psh, K, (const float *)scratch,
+                         N, perm, (float *)B);
+  }
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Adjoint of the transport.
 //
 //   gbar[k][c]  = sum_o dB[c](perm[o]) * V[k][o][c]
@@ -213,10 +387,20 @@ __global__ __launch_bounds__(256) void k_adj_x(const float *__restrict__ Y, int 
       const float4 *ysrc = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs);
       for (int i = t; i < yq; i += 256)
         reinterpret_cast<float4 *>(Ys)[i] = (i / (Cs / 4) < nv) ? ysrc[i] : z;
-      for (int i = t; i < K * pq; i += 256) {
-        const int k = i / pq, w = i - k * pq;
-        const float4 *psrc = reinterpret_cast<const float4 *>(P + ((int64_t)k * N + o0) * Psh);
-        reinterpret_cast<float4 *>(Ps)[i] = (w / (Psh / 4) < nv) ? psrc[w] : z;
+      for (int i0 = 0; i0 < K * pq; i0 += 8 * 256) {  // eight loads in flight per thread
+        float4 r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * 256 + t;
+          const int k = i / pq, w = i - k * pq;
+          const float4 *psrc = reinterpret_cast<const float4 *>(P + ((int64_t)k * N + o0) * Psh);
+          r[u] = (i < K * pq && w / (Psh / 4) < nv) ? psrc[w] : z;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int i = i0 + u * 256 + t;
+          if (i < K * pq) reinterpret_cast<float4 *>(Ps)[i] = r[u];
+        }
       }
     }
     __syncthreads();

@@ -133,23 +133,6 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
 // Irradiance E = T L, area weight and the Haar levels inside a chunk.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-__device__ __forceinline__ f64x4 mfma16(double a, double b, f64x4 c) {
-  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-template <typename CT> struct MfmaOut;
-template <> struct MfmaOut<float> {
-  typedef f32x4 V4;
-  static __device__ __forceinline__ int row(int lk, int v) { return 4 * lk + v; }
-};
-template <> struct MfmaOut<double> {
-  typedef f64x4 V4;
-  static __device__ __forceinline__ int row(int lk, int v) { return lk + 4 * v; }
-};
-
 constexpr int TL_CH = 256;
 constexpr int TL_STRIDE = 17;
 

@@ -112,6 +112,12 @@ int tile_kstep(int vdt);
 hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
                           const int32_t *perm, void *B, bool fp64, hipStream_t st);
 
+// Folded lighting transport: B = sum_k g_k P_k L (P_k = W_k H (A o T)).
+hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
+                         const void *sh, Cols cols, int N, const int32_t *perm, void *B, bool fp64,
+                         void *scratch, hipStream_t st);
+size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64);
+
 // Adjoint: partial sums over vertex blocks, then the final reduction.
 hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, int Psh,
                           const void *gcol, const double *dg64, const int32_t *perm, int N, int K,

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtlt.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 WAVELET_NONE, WAVELET_HAAR = 0, 1
-SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS = 1, 2, 4
+SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS, FOLDED_LIGHTING = 1, 2, 4, 8
 LAYOUTS = {"auto": 0, "rows": 1, "tiles": 2}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
@@ -290,13 +290,13 @@ class Renderer:
         import torch
         return torch.float64 if self.fp64 else torch.float32
 
-    def render(self, out=None, save=False, force=False, plain=False):
+    def render(self, out=None, save=False, force=False, plain=False, folded=False):
         import torch
         if out is None:
             out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
                               device=self.torch_device)
         flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0) | \
-            (PLAIN_ROWS if plain else 0)
+            (PLAIN_ROWS if plain else 0) | (FOLDED_LIGHTING if folded else 0)
         _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags), self._h)
         return out
 

@@ -110,6 +110,38 @@ def test_full_size_sampled_rows(name, n_rows):
     r.close()
 
 
+@pytest.mark.parametrize("name,kw", [("dense-f64-642", {}),
+                                     ("haar-f32-10242:batched", dict(subdiv=4, n_light=5, n_cfg=5)),
+                                     ("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=64, n_cfg=64)),
+                                     ("large-f16-163842:shrunk", dict(subdiv=4, n_light=16, n_cfg=1))],
+                         ids=["dense-f64-642", "haar-f32-10242:batched", "batch64-bf16-40962:shrunk",
+                              "large-f16-163842:shrunk"])
+def test_folded_lighting_equals_transport(name, kw):
+    """The folded lighting transport B = sum_k g_k P_k L equals the wavelet
+    transport of the same kept coefficients (and so the oracle)."""
+    w = _workload(name, kw)
+    say(f"[folded] {name}")
+    r, L, th, B = _render(w)
+    r.set_lighting(dev_tensor(L, light_dtype(w)))
+    r.set_material(dev_tensor(th, "f64"))
+    Bf = r.render(force=True, folded=True).cpu().numpy()
+    ref = oracle_scene(w).render(L, th)
+    e_t, e_o = normwise(Bf, B), normwise(Bf, ref)
+    say(f"[folded] {name}: vs transport {e_t:.3e}, vs oracle {e_o:.3e}")
+    # both forms carry Ehat (and G) at ~16 significant bits with 16-bit storage
+    tol = {"f64": 1e-10, "f32": 2e-6, "f16": 1e-5, "bf16": 1e-4}[w.storage]
+    assert e_t <= tol, e_t
+    assert e_o <= TOL[w.storage], e_o
+    # a material edit through the folded path
+    th2 = synth.make_materials(w, seed=4242)
+    r.set_material(dev_tensor(th2, "f64"))
+    Bm = r.render(folded=True).cpu().numpy()
+    assert normwise(Bm, oracle_scene(w).render(L, th2)) <= TOL[w.storage]
+    with pytest.raises(tlt.TltError):
+        r.render(folded=True, save=True)
+    r.close()
+
+
 def test_untruncated_wavelet_equals_plain_fp64():
     """Eq. (8): with nothing truncated the Haar form equals the plain form."""
     w = synth.get("dense-f64-642")
