@@ -291,10 +291,7 @@ __global__ __launch_bounds__(256) void k_adj_partial(
 //                  the contraction index kappa = (k, o):
 //                  X[c][lm] += sum_kappa (g[k][c] Y[o][c]) * P[k][o][lm],
 //                  v_mfma_f32_16x16x4f32 (exact float32 products, float32
-//                  accumulation), operands staged in LDS ADJ_SUB vertices at
-//                  a time with float4 loads; each 16x16 (c, lm) tile belongs
-//                  to one wave and is summed in LDS over the block.
-constexpr int ADJ_SUB = 32;
+//                  accumulation).
 
 __global__ __launch_bounds__(256) void k_adj_permute(const float *__restrict__ dB,
                                                      const int32_t *__restrict__ perm, int N, int C,
@@ -355,78 +352,115 @@ __global__ __launch_bounds__(256) void k_adj_gbar(const float *__restrict__ V,
   }
 }
 
-size_t adjoint_x_lds(int K, int n_sh, int C, int Cs, int Psh) {
-  return sizeof(float) * ((size_t)ADJ_SUB * Cs + (size_t)K * ADJ_SUB * Psh + (size_t)K * Cs +
-                          (size_t)C * n_sh);
-}
-
+// X partials of block b and column group blockIdx.y (64 columns): every wave
+// takes a quarter of the block's vertices, four at a time, and for each term
+// k multiplies A = (g_k[c] Y[o][c]) by B = P_k[o][lm] into its (c, lm) tiles
+// (MTN x NTN tiles of 16x16 in registers).  Loads carry no branches:
+// addresses are clamped, values past the ends zeroed.  The four waves'
+// tiles are then added in wave order through LDS.
+template <int MTN, int NTN, int KT>
 __global__ __launch_bounds__(256) void k_adj_x(const float *__restrict__ Y, int Cs,
                                                const float *__restrict__ P, int Psh,
                                                const float *__restrict__ gcol, int N, int K,
                                                int n_sh, int C, int nout, int vb,
                                                float *__restrict__ part) {
-  extern __shared__ __align__(16) float adj_sm[];
-  float *Ys = adj_sm;                           // [ADJ_SUB][Cs]
-  float *Ps = Ys + (size_t)ADJ_SUB * Cs;        // [K][ADJ_SUB][Psh]
-  float *gl = Ps + (size_t)K * ADJ_SUB * Psh;   // [K][Cs]
-  float *X = gl + (size_t)K * Cs;               // [C][n_sh]
+  __shared__ float red[64 * 64];
+  __shared__ float gl[16 * 64];   // K <= 16
   const int t = threadIdx.x;
-  const int b = blockIdx.x;
+  const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int b = blockIdx.x, cg0 = blockIdx.y * 64;
   const int n_g = K * C;
-  const int wave = t >> 6, lane = t & 63;
-  const int mtc = (C + 15) / 16, ntl = (n_sh + 15) / 16;
-  for (int i = t; i < K * Cs; i += 256) gl[i] = (i % Cs) < C ? gcol[i] : 0.f;
-  for (int i = t; i < C * n_sh; i += 256) X[i] = 0.f;
-  const int yq = ADJ_SUB * Cs / 4, pq = ADJ_SUB * Psh / 4;  // float4 per sub-block
-  for (int sb = 0; sb < vb / ADJ_SUB; ++sb) {
-    const int o0 = b * vb + sb * ADJ_SUB;
-    const int nv = max(0, min(ADJ_SUB, N - o0));
-    __syncthreads();  // previous sub-block done with Ys and Ps
-    {
-      const float4 z = {0.f, 0.f, 0.f, 0.f};
-      const float4 *ysrc = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs);
-      for (int i = t; i < yq; i += 256)
-        reinterpret_cast<float4 *>(Ys)[i] = (i / (Cs / 4) < nv) ? ysrc[i] : z;
-      for (int i0 = 0; i0 < K * pq; i0 += 8 * 256) {  // eight loads in flight per thread
-        float4 r[8];
+  for (int i = t; i < K * 64; i += 256) {
+    const int c = cg0 + (i & 63);
+    gl[i] = c < C ? gcol[(size_t)(i >> 6) * Cs + c] : 0.f;
+  }
+  __syncthreads();
+  const int per = vb / 4;
+  const int ow0 = b * vb + wave * per;
+  const int ow1 = min(ow0 + per, N);
+  f32x4 acc[MTN][NTN];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = i0 + u * 256 + t;
-          const int k = i / pq, w = i - k * pq;
-          const float4 *psrc = reinterpret_cast<const float4 *>(P + ((int64_t)k * N + o0) * Psh);
-          r[u] = (i < K * pq && w / (Psh / 4) < nv) ? psrc[w] : z;
+  for (int m = 0; m < MTN; ++m)
+#pragma unroll
+    for (int n = 0; n < NTN; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int ycol[MTN];
+#pragma unroll
+  for (int m = 0; m < MTN; ++m) ycol[m] = min(cg0 + m * 16 + li, Cs - 1);
+  int pcol[NTN];
+  bool pok[NTN];
+#pragma unroll
+  for (int n = 0; n < NTN; ++n) {
+    pok[n] = n * 16 + li < n_sh;
+    pcol[n] = min(n * 16 + li, Psh - 1);
+  }
+  for (int o = ow0; o < ow1; o += 4) {
+    const int orow = o + lk;
+    const bool ook = orow < ow1;
+    const int oc = min(orow, N - 1);
+    float yv[MTN];
+#pragma unroll
+    for (int m = 0; m < MTN; ++m) yv[m] = Y[(int64_t)oc * Cs + ycol[m]];
+    float pv[KT][NTN];   // KT >= K; rows past K repeat row K-1 and are not used
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+#pragma unroll
+      for (int n = 0; n < NTN; ++n) pv[k][n] = P[((int64_t)min(k, K - 1) * N + oc) * Psh + pcol[n]];
+#pragma unroll
+    for (int m = 0; m < MTN; ++m) yv[m] = ook ? yv[m] : 0.f;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < K) {
+#pragma unroll
+        for (int m = 0; m < MTN; ++m) {
+          const float a = gl[k * 64 + m * 16 + li] * yv[m];
+#pragma unroll
+          for (int n = 0; n < NTN; ++n)
+            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, pok[n] ? pv[k][n] : 0.f, acc[m][n], 0, 0, 0);
         }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int i = i0 + u * 256 + t;
-          if (i < K * pq) reinterpret_cast<float4 *>(Ps)[i] = r[u];
-        }
-      }
-    }
-    __syncthreads();
-    for (int tile = wave; tile < mtc * ntl; tile += 4) {
-      const int mt = tile / ntl, nt = tile - mt * ntl;
-      const int c = mt * 16 + (lane & 15);
-      const int lm = nt * 16 + (lane & 15);
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 8
-      for (int s = 0; s < K * ADJ_SUB / 4; ++s) {
-        const int kap = s * 4 + (lane >> 4);
-        const int k = kap / ADJ_SUB, ol = kap - k * ADJ_SUB;
-        const float a = gl[k * Cs + c] * Ys[ol * Cs + c];
-        const float bv = lm < n_sh ? Ps[(k * ADJ_SUB + ol) * Psh + lm] : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cc = mt * 16 + 4 * (lane >> 4) + v;
-        const int ll = nt * 16 + (lane & 15);
-        if (cc < C && ll < n_sh) X[cc * n_sh + ll] += acc[v];
       }
     }
   }
-  __syncthreads();
-  for (int i = t; i < C * n_sh; i += 256) part[(size_t)b * nout + n_g + i] = X[i];
+  // the four waves' tiles, added in wave order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int m = 0; m < MTN; ++m)
+#pragma unroll
+        for (int n = 0; n < NTN; ++n)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int idx = (m * 16 + 4 * lk + v) * 64 + n * 16 + li;
+            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[m][n][v];
+          }
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < 64 * 64; i += 256) {
+    const int cl = i >> 6, lm = i & 63, c = cg0 + cl;
+    if (c < C && lm < n_sh) part[(size_t)b * nout + n_g + (size_t)c * n_sh + lm] = red[i];
+  }
+}
+
+template <int MTN, int KT>
+static void adj_x_go(int ntn, dim3 g, hipStream_t st, const float *Y, int Cs, const float *P, int Psh,
+                     const float *gcol, int N, int K, int n_sh, int C, int nout, int vb, float *part) {
+  switch (ntn) {
+#define ADJX(n)                                                                                 \
+  case n:                                                                                       \
+    TLT_LAUNCH((k_adj_x<MTN, n, KT>), g, dim3(256), 0, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, \
+               nout, vb, part);                                                                 \
+    break;
+    ADJX(1) ADJX(2) ADJX(3) ADJX(4)
+#undef ADJX
+  }
+}
+
+template <int MTN>
+static void adj_x_k(int ntn, dim3 g, hipStream_t st, const float *Y, int Cs, const float *P, int Psh,
+                    const float *gcol, int N, int K, int n_sh, int C, int nout, int vb, float *part) {
+  if (K <= 4) adj_x_go<MTN, 4>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
+  else if (K <= 8) adj_x_go<MTN, 8>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
+  else adj_x_go<MTN, 16>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
 }
 
 // Sum of the per-block partials in a fixed order, in float64.  Stage 1:
@@ -517,16 +551,23 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
     TLT_LAUNCH(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, nblk,
                        nout, stage1);
   } else {
-    const size_t lds = adjoint_x_lds(K, n_sh, C, Cs, Psh);
-    if (lds > 160 * 1024 || Cs % 16 != 0 || Cs > 1024 || Psh % 4 != 0) return hipErrorInvalidValue;
+    if (Cs % 16 != 0 || Cs > 1024 || Psh > 64 || K > 16 || n_sh > 64) return hipErrorInvalidValue;
     float *Y = (float *)((char *)partial + l.y);
     const int64_t ny = (int64_t)N * Cs;
     TLT_LAUNCH(k_adj_permute, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st,
                        (const float *)dB, perm, N, C, Cs, Y);
     TLT_LAUNCH(k_adj_gbar, dim3(nblk, K), dim3(256), 0, st, (const float *)V, Y, Cs, N, C,
                        nout, vb, (float *)partial);
-    TLT_LAUNCH(k_adj_x, dim3(nblk), dim3(256), lds, st, Y, Cs, (const float *)P, Psh,
-                       (const float *)gcol, N, K, n_sh, C, nout, vb, (float *)partial);
+    {
+      const dim3 gx(nblk, (C + 63) / 64);
+      const int mtn = (std::min(64, C) + 15) / 16, ntn = (n_sh + 15) / 16;
+      const float *Pf = (const float *)P, *gf = (const float *)gcol;
+      float *pf = (float *)partial;
+      if (mtn == 1) adj_x_k<1>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
+      else if (mtn == 2) adj_x_k<2>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
+      else if (mtn == 3) adj_x_k<3>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
+      else adj_x_k<4>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
+    }
     TLT_LAUNCH(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, nblk,
                        nout, stage1);
   }
