@@ -209,6 +209,20 @@ tlt_status set_material(tlt_ctx *ctx, int n_mat, const double *theta_dev,
 tlt_status set_lighting(tlt_ctx *ctx, int n_light, const void *sh_dev);
 
 /*
+ * Per-frame irradiance supplied directly, in place of SH lighting (for
+ * lights the SH transfer does not represent, e.g. irradiance from a shadow
+ * map; Step 1 of Sec. 4 computes E, and any E may enter the transport):
+ * E_dev [n_light][N][3] in device memory, original vertex order, float64
+ * for an F64 transport else float32, read by render on its stream (valid
+ * until that render completes).  Render then computes
+ * Ehat = Haar(pad(A o E)) and the transport as usual.  Stays in effect
+ * until set_lighting.  render_backward and TLT_FOLDED_LIGHTING need SH
+ * lighting (TLT_E_STATE / TLT_E_ARG after this call).  TLT_E_STATE before
+ * load_transport, TLT_E_ARG for n_light < 1 or NULL.
+ */
+tlt_status set_irradiance(tlt_ctx *ctx, int n_light, const void *E_dev);
+
+/*
  * Renders B [n_out][N][3] (original vertex order, float64 for an F64
  * transport else float32) into caller-owned device memory on hip_stream.
  * Recomputes only what changed since the last render (a material change

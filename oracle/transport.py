@@ -71,12 +71,19 @@ class Scene:
         w = self.w
         return np.stack([self.T @ L[light_of(w, q)] for q in range(w.n_out)])
 
-    def ehat(self, L):
-        """Ehat[q, j, ch]: Haar of the area-weighted Morton-ordered E."""
-        E = self.irradiance(L)[:, self.perm, :] * self.area[self.perm][None, :, None]
+    def ehat(self, L=None, E=None):
+        """Ehat[q, j, ch]: Haar of the area-weighted Morton-ordered E, with
+        E = T L from SH lighting L, or a given irradiance E[light, i, ch]
+        (original vertex order; output set q uses light(q))."""
+        if E is None:
+            Eq = self.irradiance(L)
+        else:
+            E = np.asarray(E, dtype=np.float64)
+            Eq = np.stack([E[light_of(self.w, q)] for q in range(self.w.n_out)])
+        Ew = Eq[:, self.perm, :] * self.area[self.perm][None, :, None]
         if self.wavelet == "none":
-            return E
-        return haar.haar(haar.pad(E, self.n_pad, axis=1), axis=1)
+            return Ew
+        return haar.haar(haar.pad(Ew, self.n_pad, axis=1), axis=1)
 
     # -- material side ----------------------------------------------------
     def g(self, theta):
@@ -137,13 +144,13 @@ class Scene:
         return np.einsum("kpn,qkpnc->kqpc", vals, Eh[:, cols, :])
 
     # -- radiance ---------------------------------------------------------
-    def render_rows(self, L, theta, p_rows, block=64, keep_v=False):
+    def render_rows(self, L, theta, p_rows, block=64, keep_v=False, E=None):
         """O-B radiance at Morton positions p_rows -> B[q, len(p_rows), ch].
 
         With keep_v also returns v[k, q, P, ch] = sum_j W_k[p, j] Ehat[q, j, ch].
         """
         w = self.w
-        Eh = self.ehat(L)                       # [n_out, n, 3]
+        Eh = self.ehat(L, E)                    # [n_out, n, 3]
         g = self.g(theta)                       # [n_cfg, 3, K]
         G = np.stack([g[mat_of(w, q)] for q in range(w.n_out)])   # [n_out,3,K]
         p_rows = np.asarray(p_rows)
@@ -157,9 +164,9 @@ class Scene:
                 V[:, :, s:s + len(pr), :] = v
         return (B, V) if keep_v else B
 
-    def render(self, L, theta, block=64):
+    def render(self, L, theta, block=64, E=None):
         """O-B radiance for every vertex, original order -> [n_out, N, 3]."""
-        Bm = self.render_rows(L, theta, np.arange(self.N), block=block)
+        Bm = self.render_rows(L, theta, np.arange(self.N), block=block, E=E)
         B = np.empty_like(Bm)
         B[:, self.perm, :] = Bm
         return B

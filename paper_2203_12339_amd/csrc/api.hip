@@ -54,6 +54,8 @@ struct tlt_ctx {
 
   // inputs of the next render
   const void *sh = nullptr;
+  const void *E = nullptr;   // supplied irradiance (set_irradiance) instead of SH lighting
+  bool use_E = false;
   int n_light = 0;
   const double *theta = nullptr;
   int n_mat = 0;
@@ -853,6 +855,19 @@ tlt_status set_lighting(tlt_ctx *c, int n_light, const void *sh_dev) {
   if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_lighting before load_transport");
   if (n_light < 1 || !sh_dev) return fail(&c->err, TLT_E_ARG, "need n_light >= 1 and a pointer");
   c->sh = sh_dev;
+  c->use_E = false;
+  c->n_light = n_light;
+  c->light_dirty = true;
+  c->v_valid = false;
+  return TLT_OK;
+}
+
+tlt_status set_irradiance(tlt_ctx *c, int n_light, const void *E_dev) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_irradiance before load_transport");
+  if (n_light < 1 || !E_dev) return fail(&c->err, TLT_E_ARG, "need n_light >= 1 and a pointer");
+  c->E = E_dev;
+  c->use_E = true;
   c->n_light = n_light;
   c->light_dirty = true;
   c->v_valid = false;
@@ -862,7 +877,8 @@ tlt_status set_lighting(tlt_ctx *c, int n_light, const void *sh_dev) {
 tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
   if (!c->loaded) return fail(&c->err, TLT_E_STATE, "render before load_transport");
-  if (!c->sh || !c->theta) return fail(&c->err, TLT_E_STATE, "render before set_lighting/set_material");
+  if (!(c->use_E ? c->E : c->sh) || !c->theta)
+    return fail(&c->err, TLT_E_STATE, "render before set_lighting (or set_irradiance) / set_material");
   if (!B) return fail(&c->err, TLT_E_ARG, "B is NULL");
   if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
     return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
@@ -870,6 +886,8 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     return fail(&c->err, TLT_E_ARG, "unknown flags");
   if ((flags & TLT_FOLDED_LIGHTING) && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS)))
     return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING excludes TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS");
+  if ((flags & TLT_FOLDED_LIGHTING) && c->use_E)
+    return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING needs SH lighting, not a supplied irradiance");
   hipStream_t st = (hipStream_t)stream;
   tlt_status s;
   if ((s = ensure_columns(c)) != TLT_OK) return s;
@@ -916,7 +934,12 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     HIPC(c, launch_combine(c->V, c->Cs, c->gcol, c->K, c->N, c->C, c->perm, B, c->fp64, st));
   } else {
     a.n_tl_blocks = c->n_chunks * (c->Cs / 16);
-    a.sh = c->sh;
+    if (c->use_E) {
+      a.E = c->E;
+      a.perm = c->perm;
+    } else {
+      a.sh = c->sh;
+    }
     a.ehat = c->ehat;
     a.partial = c->partial;
     a.ehat2 = c->ehat2;
@@ -956,6 +979,8 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
   if (!c->loaded || !c->v_valid || !c->have_P || c->mat_dirty || c->light_dirty)
     return fail(&c->err, TLT_E_STATE,
                 "render_backward needs a render with TLT_SAVE_FOR_BACKWARD of the current inputs");
+  if (c->use_E)
+    return fail(&c->err, TLT_E_STATE, "render_backward needs SH lighting, not a supplied irradiance");
   if (!dB || !dSH || !dTheta) return fail(&c->err, TLT_E_ARG, "NULL gradient pointer");
   hipStream_t st = (hipStream_t)stream;
   const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->Cs, c->fp64);

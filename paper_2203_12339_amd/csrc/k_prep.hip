@@ -181,12 +181,29 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   uint32_t *ehat2 = (uint32_t *)a.ehat2;
   CT *partial = (CT *)a.partial;
 
+  const int nr_e = max(0, min(a.ch_rows, a.N - i0));
+  if (a.E != nullptr) {
+    // supplied irradiance: E at the chunk's vertices (gathered through the
+    // Morton permutation) times the area, in place of T L
+    const CT *E = (const CT *)a.E;
+    for (int idx = threadIdx.x; idx < a.ch_rows * 16; idx += 256) {
+      const int lr = idx >> 4, n = idx & 15, c = c0 + n;
+      CT v = 0;
+      if (lr < nr_e && c < a.cols.C) {
+        const int q = c / 3, ch = c - 3 * q;
+        const int l = a.cols.n_light > 1 ? q : 0;
+        const int64_t o = a.perm[i0 + lr];
+        v = E[((int64_t)l * a.N + o) * 3 + ch] * area[i0 + lr];
+      }
+      x[lr * TL_STRIDE + n] = v;
+    }
+  }
   // Stage everything the chunk reads with one batch of loads.  The chunk's
   // transfer rows are one contiguous range of T, read as 16-byte vectors
   // through a buffer resource (reads past the end of T return zeros), all
   // issued before any is used.
-  const int nr = max(0, min(a.ch_rows, a.N - i0));         // real vertices of the chunk
-  {
+  const int nr = nr_e;                                      // real vertices of the chunk
+  if (a.E == nullptr) {
     constexpr int TSZ = sizeof(TT), VEC = 16 / TSZ, VPT = 8;
     const int nel = nr * a.n_sh;                            // elements of the chunk
     const int nvec = (nel + VEC - 1) / VEC;
@@ -223,7 +240,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
     for (int idx = threadIdx.x; idx < a.ch_rows; idx += 256) As[idx] = idx < nr ? area[i0 + idx] : CT(0);
   }
   __syncthreads();
-  if (64 * wave < a.ch_rows) {
+  if (a.E == nullptr && 64 * wave < a.ch_rows) {
     V4 acc[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc[u] = V4{0, 0, 0, 0};

@@ -51,6 +51,8 @@ struct PrepArgs {
   const void *T;           // [N][n_sh] storage tdt
   int N, n_sh, n_shp;
   const void *sh;          // [n_light][n_sh][3] compute precision; nullptr = identity
+  const void *E;           // or: irradiance [n_light][N][3] (original order), replaces T L
+  const int32_t *perm;     // Morton position -> original vertex id (with E)
   const void *area;        // [N] compute precision
   int haar, ch_rows, n_rows, n_chunks;
   void *ehat;              // [n_rows][Cs]

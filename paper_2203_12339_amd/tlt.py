@@ -89,6 +89,7 @@ _set_tile = _sig("tlt_set_tile", ctypes.c_int, _p, ctypes.c_int)
 _get_tile = _sig("tlt_get_tile", ctypes.c_int, _p)
 _version = _sig("tlt_version", ctypes.c_char_p)
 _set_tuning = _sig("tlt_set_tuning", ctypes.c_int, _p, ctypes.c_int32, ctypes.c_int32)
+_set_irradiance = _sig("set_irradiance", ctypes.c_int, _p, ctypes.c_int, _p)
 _profile_enable = _sig("tlt_profile_enable", ctypes.c_int, _p, ctypes.c_int)
 _profile_read = _sig("tlt_profile_read", ctypes.c_int, _p, ctypes.c_int,
                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64))
@@ -99,7 +100,7 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
-            "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read"]
+            "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance"]
 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
 TUNING_KEYS = {"tile_chunk": TUNE_TILE_CHUNK, "stream_waves_per_cu": TUNE_STREAM_WAVES_PER_CU,
@@ -263,6 +264,17 @@ class Renderer:
         return self
 
     # -- inputs -----------------------------------------------------------
+    def set_irradiance(self, E):
+        """E: CUDA tensor [n_light, N, 3] (original vertex order; float64 for
+        F64 storage) used instead of SH lighting until set_lighting."""
+        import torch
+        want = torch.float64 if self.fp64 else torch.float32
+        assert E.is_cuda and E.dtype == want and E.is_contiguous(), (E.dtype, want)
+        assert E.shape[1] == self.N and E.shape[2] == 3
+        self._E = E
+        self.n_light = E.shape[0]
+        return _check(_set_irradiance(self._h, E.shape[0], ctypes.c_void_p(E.data_ptr())), self._h)
+
     def set_material(self, theta):
         """theta: CUDA float64 tensor [n_mat, 3, 3]. Returns the status."""
         import torch

@@ -112,7 +112,8 @@ def seeds(w: Workload) -> dict:
     """Per-purpose seeds of a workload."""
     return dict(mesh=12339 + w.seed, light=22030 + w.seed,
                 material=31000 + w.seed, rows=41000 + w.seed,
-                target=51000 + w.seed, probe=61000 + w.seed)
+                target=51000 + w.seed, probe=61000 + w.seed,
+                irradiance=71000 + w.seed)
 
 
 # ---------------------------------------------------------------------------
@@ -192,6 +193,15 @@ def make_lighting(w: Workload, n_light: int | None = None, seed=None):
     L = rng.standard_normal((n, w.n_sh, 3))
     L[:, 0, :] = np.abs(L[:, 0, :])
     return L
+
+
+def make_irradiance(w: Workload, n_light: int | None = None, seed=None):
+    """A per-vertex irradiance [n_light, N, 3] ~ U(0, 2), original vertex
+    order: an input supplied in place of SH lighting (e.g. from a shadowing
+    or local-light pass)."""
+    n = w.n_light if n_light is None else n_light
+    rng = np.random.default_rng(seeds(w)["irradiance"] if seed is None else seed)
+    return rng.uniform(0.0, 2.0, size=(n, w.n_vertices, 3))
 
 
 def make_materials(w: Workload, n_cfg: int | None = None, seed=None):

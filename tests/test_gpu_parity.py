@@ -212,6 +212,52 @@ def test_linearity_and_material_only_update():
     r.close()
 
 
+@pytest.mark.parametrize("name,kw", [("dense-f64-642", {}),
+                                     ("haar-f32-10242:small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
+                                     ("haar-f32-10242", {}),
+                                     ("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=64, n_cfg=64))],
+                         ids=["dense-f64-642", "haar-f32-small-ragged", "haar-f32-10242",
+                              "batch64-bf16-shrunk"])
+def test_supplied_irradiance(name, kw):
+    """Irradiance handed in instead of SH lighting: E = T L reproduces the SH
+    path; an arbitrary E matches the oracle; the SH-only paths refuse it."""
+    w = _workload(name, kw)
+    say(f"[irradiance] {name}: N={w.n_vertices} n_light={w.n_light} storage={w.storage}")
+    dt = light_dtype(w)
+    sc = oracle_scene(w)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    r, _, _, B0 = _render(w, L=L, th=th)
+    E_tl = np.stack([sc.T @ L[l] for l in range(w.n_light)])
+    r.set_irradiance(dev_tensor(E_tl, dt))
+    B1 = r.render(force=True).cpu().numpy()
+    e01 = normwise(B1, B0)
+    E = synth.make_irradiance(w)
+    r.set_irradiance(dev_tensor(E, dt))
+    B2 = r.render(force=True).cpu().numpy()
+    ref = sc.render(None, th, E=E)
+    e2 = normwise(B2, ref)
+    say(f"[irradiance] {name}: E=TL vs SH {e01:.3e}; random E vs oracle {e2:.3e}")
+    assert e01 <= TOL[w.storage], e01
+    assert e2 <= TOL[w.storage], e2
+    if w.storage != "f64":
+        B3 = r.render(force=True, plain=True).cpu().numpy()
+        assert normwise(B3, ref) <= TOL[w.storage]
+        with pytest.raises(tlt.TltError) as ei:
+            r.render(force=True, folded=True)
+        assert ei.value.status == -1
+    r.render(save=True, force=True)
+    with pytest.raises(tlt.TltError) as ei:
+        r.render_backward(torch.zeros((w.n_out, w.n_vertices, 3), device="cuda:0",
+                                      dtype=torch.float64 if w.storage == "f64" else torch.float32))
+    assert ei.value.status == -2
+    # back to SH lighting: the SH path again
+    r.set_lighting(dev_tensor(L, dt))
+    B4 = r.render(force=True).cpu().numpy()
+    assert normwise(B4, B0) <= (1e-13 if w.storage == "f64" else 1e-6)
+    r.close()
+
+
 def test_autograd_fp64_gradients():
     """Gradient of the L2 loss vs the FP64 oracle adjoint and central FD."""
     from oracle import adjoint

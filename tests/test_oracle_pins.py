@@ -340,6 +340,32 @@ def test_linearity_and_reciprocity():
     np.testing.assert_allclose(lhs, rhs, rtol=1e-11)
 
 
+def test_supplied_irradiance_path():
+    """Step 1 of Sec. 4 with E given instead of T L: E = T L reproduces the
+    SH path; Haar of A*E keeps the energy (orthonormal) and its scaling
+    coefficient is the area-weighted sum over sqrt(n_pad); untruncated, the
+    radiance is the dense sum of Eq. (7) over the PCA kernels."""
+    w = synth.get("dense-f64-642").with_(subdiv=1, n_light=2, n_cfg=2, keep=None, wavelet="haar")
+    s = Scene(w)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    E_tl = np.stack([s.T @ L[l] for l in range(w.n_light)])
+    np.testing.assert_allclose(s.ehat(E=E_tl), s.ehat(L), rtol=0, atol=1e-13)
+    E = synth.make_irradiance(w)
+    assert E.shape == (2, s.N, 3) and E.min() >= 0
+    Eh = s.ehat(E=E)
+    AE = E * s.area[None, :, None]
+    np.testing.assert_allclose((Eh ** 2).sum(axis=1), (AE ** 2).sum(axis=1), rtol=1e-12)
+    np.testing.assert_allclose(Eh[:, 0, :], AE.sum(axis=1) / np.sqrt(s.n_pad), rtol=1e-12)
+    B = s.render(None, th, E=E)
+    g = s.g(th)                                            # [m, ch, k]
+    Kr = s.kernel_rows(np.arange(s.N))                     # [k, p, p'] Morton order
+    AEm = AE[:, s.perm, :]
+    ref = np.einsum("qck,kpr,qrc->qpc", g, Kr, AEm)
+    Bm = B[:, s.perm, :]
+    np.testing.assert_allclose(Bm, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
 def test_selection_matches_brute_force_sort():
     w = synth.get("dense-f64-642").with_(subdiv=1, keep=0.25, wavelet="haar")
     s = Scene(w)
