@@ -81,6 +81,76 @@ def cpu_baseline(w, L, th, budget_s=12.0):
     return rows, ref, dt
 
 
+def _quantiles(ms):
+    import numpy as np
+    a = np.asarray(ms)
+    return {"median_ms": round(float(np.median(a)), 5), "p10_ms": round(float(np.percentile(a, 10)), 5),
+            "p90_ms": round(float(np.percentile(a, 90)), 5), "n": int(a.size)}
+
+
+def per_step_timing(args, r, step, B):
+    """Per-step time distributions, each step bracketed by events on the
+    launch stream: warm (back to back), cold (a read of a scratch buffer evicts the
+    Infinity Cache before every step, outside the bracket) and
+    replay of the step captured once as a HIP graph (its output checked
+    against the eager one)."""
+    import torch
+    n = args.dist_steps
+    cur = torch.cuda.current_stream
+
+    def bracketed(fn, pre=None):
+        ms = []
+        for i in range(n):
+            if pre is not None:
+                pre(i)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(cur())
+            fn()
+            e1.record(cur())
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return ms
+
+    out = {"warm": _quantiles(bracketed(step))}
+    # a read of the scratch evicts the caches without leaving dirty lines
+    # whose write-back would compete with the step
+    scratch = torch.ones(args.evict_mib << 18, dtype=torch.float32, device=B.device)
+    sink = torch.empty((), dtype=torch.float32, device=B.device)
+    r.profile(True)
+    out["cold"] = _quantiles(bracketed(step, pre=lambda i: torch.sum(scratch, dim=0, out=sink)))
+    ms_tr, n_tr = r.profile_read("transport")
+    r.profile(False)
+    out["cold"]["evict_mib"] = args.evict_mib
+    out["cold"]["transport_us"] = round(1e3 * ms_tr / max(n_tr, 1), 2)
+    del scratch
+    torch.cuda.synchronize()
+    eager = B.clone()
+    try:
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(cur())
+        with torch.cuda.stream(side):
+            step()
+        cur().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            step()
+        torch.cuda.synchronize()
+        B.zero_()
+        gms = bracketed(g.replay)
+        torch.cuda.synchronize()
+        diff = float((B - eager).abs().max() / eager.abs().max().clamp_min(1e-300))
+        out["graph"] = dict(_quantiles(gms), max_rel_diff_vs_eager=diff)
+        del g
+    except Exception as e:  # pragma: no cover - reported, not fatal
+        out["graph"] = {"error": str(e)[:200]}
+    torch.cuda.synchronize()
+    log("[bench] per-step: " + "; ".join(
+        f"{k} median {v['median_ms']:.4f} ms (p10 {v['p10_ms']:.4f}, p90 {v['p90_ms']:.4f})"
+        for k, v in out.items() if "median_ms" in v))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +166,10 @@ def main():
                     help="use the (column, value) row kernel instead of the tiles")
     ap.add_argument("--folded", action="store_true",
                     help="relight through the folded lighting transport B = sum_k g_k P_k L")
+    ap.add_argument("--dist-steps", type=int, default=100,
+                    help="steps of the per-step timing passes (warm, cold, graph replay); 0 skips them")
+    ap.add_argument("--evict-mib", type=int, default=512,
+                    help="scratch read before each cold step (evicts the 256 MB Infinity Cache)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -183,6 +257,8 @@ def main():
     log(f"[bench] {args.steps} steps in {elapsed:.3f}s -> {ms_per_step:.4f} ms/step; "
         + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in stage_ms.items()))
 
+    timing = per_step_timing(args, r, step, B) if args.dist_steps > 0 else None
+
     # roofline of the dominant kernel (the transport)
     C = 3 * w.n_out
     vsz = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[w.storage]
@@ -207,6 +283,11 @@ def main():
                 "traffic": traffic, "kernel": kernel,
                 "kernel_us": round(avg_s * 1e6, 2), "kernel_launches_timed": n_tr,
                 "algorithmic_bytes": alg_bytes}
+    if timing and "transport_us" in timing.get("cold", {}):
+        cold_s = timing["cold"]["transport_us"] * 1e-6
+        roofline["cold"] = {"kernel_us": timing["cold"]["transport_us"],
+                            "achieved": round(alg_bytes / cold_s / 1e9, 1),
+                            "frac": round(alg_bytes / cold_s / 1e9 / HBM_PEAK_GBS, 4)}
     ai = flops / alg_bytes
 
     # accuracy of this very output on a sample of rows + the CPU oracle time
@@ -250,6 +331,7 @@ def main():
         },
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "timing": timing,
     }
     print(json.dumps(out), flush=True)
     r.close()
