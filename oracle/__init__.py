@@ -18,6 +18,11 @@ in plain NumPy float64, following the paper:
                    method's discrete operator (Eq. 7, 8 and Step 1 of the
                    precompute in Sec. 3.2; rendering Steps 1-4 of Sec. 4).
 * ``adjoint``   -- FP64 adjoint of O-B and its finite-difference check.
+* ``cdf97``     -- the CDF 9/7 output-side transform w_1 and its inverse
+                   (Sec. 3.2; 9/7 per Sec. 5), filters from their definition.
+* ``spatial``   -- spatial compression of the truncated rows by an energy
+                   threshold and its rendering form (Eq. 9, 10; precompute
+                   Step 2 of Sec. 3.2; Steps 2, 4, 5 of Sec. 4).
 
 Functions whose result no independent pin covers say "parity unpinned".
 """
