@@ -33,12 +33,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# sources that fix the transport kernel, its launch shape and the layout of
+# the data it reads (kept rows, tiles, irradiance coefficients)
+TRANSPORT_SOURCES = ("csrc/k_tiles.hip", "csrc/k_build.hip", "csrc/k_prep.hip",
+                     "csrc/device_common.h", "csrc/kernels.h", "csrc/api.hip", "tuning.json")
+
+
 def kernel_hash():
-    """Hash of the library sources: stored counter readings are valid only
-    for the kernels and data layout they were taken on."""
+    """Hash of the transport's sources: stored counter readings are valid
+    only for the kernel and data layout they were taken on."""
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2203_12339_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2203_12339_amd", "csrc", f), "rb") as fh:
+    for f in TRANSPORT_SOURCES:
+        with open(os.path.join(ROOT, "paper_2203_12339_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
