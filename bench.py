@@ -172,6 +172,9 @@ def main():
                     help="use the (column, value) row kernel instead of the tiles")
     ap.add_argument("--folded", action="store_true",
                     help="relight through the folded lighting transport B = sum_k g_k P_k L")
+    ap.add_argument("--spatial", type=float, default=0.0, metavar="ENERGY",
+                    help="render through the spatially compressed transport (CDF 9/7 over the "
+                         "output vertices) keeping this fraction of the coefficient energy")
     ap.add_argument("--dist-steps", type=int, default=100,
                     help="steps of the per-step timing passes (warm, cold, graph replay); 0 skips them")
     ap.add_argument("--evict-mib", type=int, default=512,
@@ -205,6 +208,20 @@ def main():
     if args.tile:
         r.set_tile(args.tile)
     log(f"[bench] precompute + load {time.perf_counter() - t0:.1f}s")
+    sp = None
+    if args.spatial:
+        if args.folded or args.backward or args.plain:
+            print("--spatial excludes --folded, --backward and --plain", file=sys.stderr)
+            sys.exit(2)
+        t0 = time.perf_counter()
+        r.load_spatial(args.spatial)
+        nnz, levels, _, e_k = r.spatial_info()
+        step1 = w.n_vertices * w.K * w.n_keep
+        sp = {"energy": args.spatial, "nnz": int(nnz), "step1_nnz": step1,
+              "kept_fraction": round(nnz / step1, 4), "levels": int(levels),
+              "precompute_s": round(time.perf_counter() - t0, 2)}
+        log(f"[bench] spatial compression: {nnz} of {step1} entries kept "
+            f"({nnz / step1:.3f}), {levels} levels, {sp['precompute_s']} s")
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
     ldt = torch.float64 if w.storage == "f64" else torch.float32
@@ -218,7 +235,8 @@ def main():
         print("--folded excludes --backward and --plain", file=sys.stderr)
         sys.exit(2)
     flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0) | \
-        (tlt.PLAIN_ROWS if args.plain else 0) | (tlt.FOLDED_LIGHTING if args.folded else 0)
+        (tlt.PLAIN_ROWS if args.plain else 0) | (tlt.FOLDED_LIGHTING if args.folded else 0) | \
+        (tlt.SPATIAL if args.spatial else 0)
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -255,7 +273,8 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     ms_tr, n_tr = r.profile_read("transport")
-    stage_ms = {s: r.profile_read(s) for s in ("weights", "irradiance", "transport", "adjoint")}
+    stage_ms = {s: r.profile_read(s) for s in ("weights", "irradiance", "transport", "adjoint")
+                + (("inverse",) if args.spatial else ())}
     r.profile(False)
     ms_per_step = 1e3 * elapsed / args.steps
     shaded = w.n_vertices * w.n_out
@@ -271,7 +290,13 @@ def main():
     esz = 8 if w.storage == "f64" else 4
     nnz = w.n_vertices * w.K * w.n_keep
     n_rows = w.n_pad if w.wavelet == "haar" else w.n_vertices
-    if args.folded:
+    if args.spatial:
+        # kept entries (column word + value) read once, Ehat read once, y
+        # written once (the inverse's own traffic is its stage's)
+        alg_bytes = sp["nnz"] * (4 + esz) + n_rows * C * esz + w.n_vertices * C * esz
+        kernel, traffic = "k_sp_rows", None
+        flops = 2.0 * sp["nnz"] * C
+    elif args.folded:
         # P_k rows read once (Psh >= n_sh columns, as stored), B written once
         psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
         alg_bytes = w.K * w.n_vertices * psh * esz + w.n_vertices * C * esz
@@ -300,7 +325,10 @@ def main():
     Bh = B.cpu().numpy()
     cpu = None
     rel_err = None
-    if not args.no_cpu_baseline:
+    if args.spatial and not args.no_cpu_baseline:
+        log("[bench] no CPU baseline for the spatial path: its oracle needs every output "
+            "coefficient (dense per-term CDF 9/7 transforms), not a sample of rows")
+    if not args.no_cpu_baseline and not args.spatial:
         log("[bench] timing the FP64 oracle on a sample of rows ...")
         rows, ref, dt = cpu_baseline(w, L, th)
         got = Bh[:, rows, :].astype(np.float64)
@@ -329,7 +357,9 @@ def main():
             "n_vertices": w.n_vertices, "K": w.K, "n_keep": w.n_keep, "n_sh": w.n_sh,
             "storage": w.storage, "lightings": w.n_light, "materials": w.n_cfg,
             "columns": C, "backward": bool(args.backward), "tile": r.tile(),
-            "layout": "folded lighting" if args.folded else ("rows" if args.plain else "tiles"),
+            "layout": ("spatial" if args.spatial else "folded lighting" if args.folded
+                       else ("rows" if args.plain else "tiles")),
+            "spatial": sp,
             "tile_shape": ({"tile_vertices": r.tuning["tile_vertices"], "tile_chunk": r.tuning["tile_chunk"],
                             "source": "autotuner table"} if getattr(r, "tuning", None) else "built-in"),
             "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),

@@ -57,7 +57,8 @@ enum {
   TLT_SAVE_FOR_BACKWARD = 1, /* keep v_k[o,c] for render_backward */
   TLT_FORCE_FULL = 2,        /* recompute every stage, ignoring dirty flags */
   TLT_PLAIN_ROWS = 4,        /* use the (column, value) row kernel even when tiles exist */
-  TLT_FOLDED_LIGHTING = 8    /* relight through P_k = W_k H (A o T): B = sum_k g_k P_k L */
+  TLT_FOLDED_LIGHTING = 8,   /* relight through P_k = W_k H (A o T): B = sum_k g_k P_k L */
+  TLT_SPATIAL = 16           /* render through the spatially compressed transport (load_spatial) */
 };
 enum { TLT_LAYOUT_AUTO = 0, TLT_LAYOUT_ROWS = 1, TLT_LAYOUT_TILES = 2 };
 
@@ -233,9 +234,92 @@ tlt_status set_irradiance(tlt_ctx *ctx, int n_light, const void *E_dev);
  * equal to the wavelet transport of the same kept coefficients up to
  * float32 rounding, reading K*N*Psh values instead of the transport
  * (incompatible with TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS: TLT_E_ARG).
+ * TLT_SPATIAL renders through the spatially compressed transport of
+ * load_spatial (Eq. 10, Steps 2, 4 and 5 of Sec. 4), recomputing every stage;
+ * TLT_E_STATE without load_spatial, TLT_E_ARG combined with
+ * TLT_SAVE_FOR_BACKWARD, TLT_PLAIN_ROWS or TLT_FOLDED_LIGHTING.
  * TLT_E_STATE before load_transport / set_material / set_lighting.
  */
 tlt_status render(tlt_ctx *ctx, void *B_dev, void *hip_stream, int flags);
+
+/*
+ * Spatial (output-side) compression -- Sec. 3.2 (Eq. 9, 10; precompute Step
+ * 2), CDF 9/7 per Sec. 5.  From the float64 Step-1 rows W_k^S (the kept
+ * (column, value) pairs of every row, as tlt_build_rows writes them for all
+ * Morton positions 0..N-1), per PCA term k:
+ *   Z_k[:, j] = w_1 W_k^S[:, j]     w_1: CDF 9/7 along the Morton-ordered
+ *                                   output index, near-orthonormal scaling
+ *                                   (low-pass DC gain sqrt 2), whole-sample
+ *                                   symmetric ends, levels while >= 8 entries
+ *                                   remain (or `levels`), coefficients laid
+ *                                   out [low_J, high_J, ..., high_1];
+ *   S2(k)     = the fewest entries of Z_k, largest |z| first (ties to the
+ *               lower u * n_cols + j), whose energy sum of z^2 reaches
+ *               `energy` times that of all of Z_k (energy = 1 keeps every
+ *               non-zero entry).
+ * Rendering with TLT_SPATIAL then computes
+ *   y[u, c] = sum_k g_k[c] sum_{j in S2(k, u)} Z_k[u, j] Ehat[j, c]
+ *   B[perm[o], c] = (w_1^{-1} y[:, c])[o]            (Step 5 of Sec. 4).
+ * Step 5 applies w_1^{-1} as a sparse matrix (a few tens of entries per
+ * output position) built here from the synthesis of every unit coefficient.
+ * The precompute runs on `threads` host threads (0 = up to 16) and
+ * transforms every column of every term densely: O(K n_cols N) host work.
+ * Values are stored in the transport's compute precision.  K < 128, else
+ * TLT_E_ARG.  TLT_E_STATE before load_transport; the compression is dropped
+ * by the next load_transport.  Host arrays are read during the call only.
+ */
+/*
+ * Host-only form of the same precompute (no GPU work): writes the CSR of the
+ * kept entries of Z over u -- rowptr_out [N+1] (always), col_out the column
+ * words (k << 24) | j and val_out the float64 values, entries of a row in
+ * (k, j) order.  col/val as in tlt_spatial_desc; n_cols = n_pad (Haar) or N.
+ * TLT_E_ARG for bad sizes or when the kept entries exceed `capacity` (call
+ * once with capacity 0 to learn rowptr_out[N]).
+ */
+tlt_status tlt_spatial_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int64_t n_keep,
+                            const int32_t *col, const double *val, double energy, int32_t levels,
+                            int64_t *rowptr_out, uint32_t *col_out, double *val_out,
+                            int64_t capacity);
+
+/*
+ * Host-only: the inverse transform w_1^{-1} of Step 5 (Sec. 4) over a list of
+ * n_vertices as a sparse matrix, CSR over the output position o:
+ * (w_1^{-1} y)[o] = sum_e w_out[e] y[col_out[e]] for e in
+ * [rowptr_out[o], rowptr_out[o+1]).  Built from the synthesis of every unit
+ * coefficient (exact zeros dropped); levels as in tlt_spatial_desc.
+ * rowptr_out [n_vertices+1] is always written; TLT_E_ARG when the entries
+ * exceed `capacity`, for n_vertices < 8 or too many levels.
+ */
+tlt_status tlt_spatial_synthesis(int32_t n_vertices, int32_t levels, int32_t *rowptr_out,
+                                 int32_t *col_out, double *w_out, int64_t capacity);
+
+typedef struct {
+  double energy;            /* retained energy fraction per term, (0, 1] */
+  int32_t levels;           /* CDF 9/7 levels, 0 = split while >= 8 entries remain */
+  int32_t threads;          /* host threads, 0 = automatic */
+  const int32_t *col;       /* [N][K][n_keep] Step-1 kept columns, ascending per row */
+  const double *val;        /* [N][K][n_keep] float64 values */
+} tlt_spatial_desc;
+
+tlt_status load_spatial(tlt_ctx *ctx, const tlt_spatial_desc *desc);
+
+/*
+ * Statistics of the loaded spatial compression: total kept entries, levels,
+ * and per term (arrays of K, each may be NULL) kept entries and retained
+ * energy fraction.  TLT_E_STATE without load_spatial.
+ */
+tlt_status tlt_spatial_info(tlt_ctx *ctx, int64_t *nnz, int32_t *levels, int64_t *nnz_k,
+                            double *energy_kept);
+
+/*
+ * Host copy of the kept entries of output coefficients u0 .. u0+n_u-1:
+ * rowptr_out [n_u+1] (relative to the first), col_out the column words
+ * (k << 24) | j, val_out the stored values widened to float64, entries of a
+ * row in (k, j) order.  rowptr_out is always written; TLT_E_ARG if the
+ * entries exceed `capacity` or the rows are out of range.  Synchronous.
+ */
+tlt_status tlt_read_spatial(tlt_ctx *ctx, int64_t u0, int64_t n_u, int64_t *rowptr_out,
+                            uint32_t *col_out, double *val_out, int64_t capacity);
 
 /*
  * Adjoint of the last render (which must have used TLT_SAVE_FOR_BACKWARD,
@@ -280,6 +364,14 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *   TLT_TUNE_STREAM_EPL          entries per lane and step of the row kernel
  *                                for narrow launches: 4, 8 or 16
  *   TLT_TUNE_STREAM_NT           1 = non-temporal loads of the rows
+ *   TLT_TUNE_SPATIAL_LANES       lanes per work item of the spatially
+ *                                compressed transport: 16, 32 or 64
+ *   TLT_TUNE_SPATIAL_UNROLL      its entries per lane and pass: 4, 8 or 16
+ *   TLT_TUNE_SPATIAL_SYNTH_LANES lanes per output position of the inverse
+ *                                transform of Step 5: 8, 16 or 32 (applies
+ *                                at the next load_spatial)
+ *   TLT_TUNE_SPATIAL_SEGMENT     longest work item of the compressed rows,
+ *                                64 .. 2^20 entries (next load_spatial)
  * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
  * key or a value out of range.  Results do not depend on the tuning beyond
  * float32 summation order.
@@ -288,7 +380,11 @@ enum {
   TLT_TUNE_TILE_CHUNK = 1,
   TLT_TUNE_STREAM_WAVES_PER_CU = 2,
   TLT_TUNE_STREAM_EPL = 3,
-  TLT_TUNE_STREAM_NT = 4
+  TLT_TUNE_STREAM_NT = 4,
+  TLT_TUNE_SPATIAL_LANES = 5,
+  TLT_TUNE_SPATIAL_UNROLL = 6,
+  TLT_TUNE_SPATIAL_SYNTH_LANES = 7,
+  TLT_TUNE_SPATIAL_SEGMENT = 8
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 
@@ -297,8 +393,9 @@ tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
  * each stage with a pair of HIP events written by the stage's own kernel
  * dispatches (on their stream): 0 = material weights g_k (Step 3),
  * 1 = irradiance and its Haar transform (Step 1), 2 = wavelet transport
- * with K-term fusion (Steps 2 and 4), 3 = adjoint reductions,
- * 4 = material-only combine.  mode 1 waits for pending events, clears the
+ * with K-term fusion (Steps 2 and 4; with TLT_SPATIAL the compressed
+ * transport), 3 = adjoint reductions, 4 = material-only combine,
+ * 5 = inverse spatial transform w_1^{-1} (Step 5, TLT_SPATIAL only).  mode 1 waits for pending events, clears the
  * totals and enables; mode 0 pauses and mode 2 resumes without waiting or
  * clearing (to time a sample of the renders of a running sequence).
  * tlt_profile_read waits for the recorded events and returns the summed

@@ -17,6 +17,7 @@
 #include "../../include/tlt.h"
 #include "host_internal.h"
 #include "kernels.h"
+#include "spatial.h"
 
 using namespace tlt;
 
@@ -82,6 +83,26 @@ struct tlt_ctx {
   void *t_val = nullptr;
   size_t t_val_bytes = 0;
 
+  // spatially compressed transport (load_spatial): CSR of the kept entries
+  // of Z_k = w_1 W_k^S over u, as work items of at most 1024 entries
+  bool spatial = false;
+  int sp_levels = 0, sp_sizes[32] = {0};
+  int64_t sp_nnz = 0;
+  std::vector<int64_t> sp_rowptr, sp_nnz_k;
+  std::vector<double> sp_energy;
+  uint32_t *sp_col = nullptr;
+  void *sp_val = nullptr;
+  int sp_items = 0;
+  int64_t *sp_item_e = nullptr;   // [2][n_items]: first and one-past-last entry
+  int sp_syn_len = 0, sp_syn_lanes = 16;   // w_1^{-1} over items, padded CSR [N][syn_len]
+  int32_t *sp_syn_col = nullptr;
+  void *sp_syn_w = nullptr;
+  void *sp_part = nullptr;        // [n_items][C] partial sums
+  size_t sp_part_bytes = 0;
+  double sp_mean_item = 0.0;      // mean entries per item
+  // launch tuning (tlt_set_tuning; 0 = built-in choice)
+  int tune_sp_lanes = 0, tune_sp_unroll = 0, tune_sp_syn_lanes = 0, tune_sp_segment = 0;
+
   // tuning (tlt_set_tuning; 0 = built-in choice)
   int tune_tile_chunk = 0, tune_waves_per_cu = 0, tune_stream_epl = 0, tune_stream_nt = 0;
 
@@ -95,8 +116,8 @@ struct tlt_ctx {
   struct Ev { int stage; hipEvent_t a, b; };
   std::vector<Ev> pending;
   std::vector<hipEvent_t> pool;
-  double prof_ms[5] = {0, 0, 0, 0, 0};
-  int64_t prof_n[5] = {0, 0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_n[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -156,13 +177,34 @@ void free_columns(tlt_ctx *c) {
   c->adj_bytes = 0;
   dfree(c->fold);
   c->fold_bytes = 0;
+  dfree(c->sp_part);
+  c->sp_part_bytes = 0;
   c->C = c->Cs = c->n_out = 0;
   c->buf_nlight = c->buf_nmat = -1;
   c->v_valid = false;
 }
 
+void free_spatial(tlt_ctx *c) {
+  dfree(c->sp_col);
+  dfree(c->sp_val);
+  dfree(c->sp_item_e);
+  dfree(c->sp_syn_col);
+  dfree(c->sp_syn_w);
+  dfree(c->sp_part);
+  c->sp_part_bytes = 0;
+  c->sp_syn_len = 0;
+  c->sp_rowptr.clear();
+  c->sp_nnz_k.clear();
+  c->sp_energy.clear();
+  c->sp_items = 0;
+  c->sp_nnz = 0;
+  c->sp_levels = 0;
+  c->spatial = false;
+}
+
 void free_all(tlt_ctx *c) {
   free_columns(c);
+  free_spatial(c);
   dfree(c->col);
   dfree(c->val);
   dfree(c->T);
@@ -874,6 +916,142 @@ tlt_status set_irradiance(tlt_ctx *c, int n_light, const void *E_dev) {
   return TLT_OK;
 }
 
+tlt_status load_spatial(tlt_ctx *c, const tlt_spatial_desc *d) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "load_spatial before load_transport");
+  if (!d || !d->col || !d->val) return fail(&c->err, TLT_E_ARG, "need the float64 Step-1 rows");
+  HIPC(c, hipSetDevice(c->device));
+  if (c->K >= SP_MAX_K) return fail(&c->err, TLT_E_ARG, "spatial compression needs K < 128");
+  free_spatial(c);
+  SpatialCsr csr;
+  const unsigned hw = std::max(1u, std::min(std::thread::hardware_concurrency(), 16u));
+  tlt_status s = spatial_build(c->N, c->n_rows, c->K, c->n_keep, d->col, d->val, d->energy,
+                               d->levels, d->threads > 0 ? d->threads : (int)hw, csr, &c->err);
+  if (s != TLT_OK) return s;
+  // work items of at most SEG entries: a longer row is cut into consecutive items
+  const int64_t SEG = c->tune_sp_segment ? c->tune_sp_segment : 1024;
+  std::vector<int64_t> item_e;
+  std::vector<int32_t> u_item((size_t)c->N + 1, 0);
+  {
+    std::vector<int64_t> ie0, ie1;
+    for (int u = 0; u < c->N; ++u) {
+      u_item[u] = (int32_t)ie0.size();
+      const int64_t a = csr.rowptr[u], b = csr.rowptr[u + 1];
+      const int n = b > a ? (int)((b - a + SEG - 1) / SEG) : 1;
+      for (int p = 0; p < n; ++p) {
+        ie0.push_back(std::min(b, a + p * SEG));
+        ie1.push_back(std::min(b, a + (p + 1) * SEG));
+      }
+    }
+    u_item[c->N] = (int32_t)ie0.size();
+    item_e = ie0;
+    item_e.insert(item_e.end(), ie1.begin(), ie1.end());
+  }
+  const int n_items = u_item[c->N];
+  // w_1^{-1} (Step 5) as a sparse matrix, expanded over the work items of
+  // each coefficient's row and stored as padded CSR rows: lanes per output
+  // position (tuning, else 16 or 32 by the longest row), rows padded to a
+  // whole number of entries per lane (a multiple of 4 beyond 8)
+  std::vector<int32_t> srp, scol;
+  std::vector<double> sw;
+  synthesis_build(c->N, csr.sizes, (int)hw, srp, scol, sw);
+  int max_len = 1;
+  for (int o = 0; o < c->N; ++o) {
+    int len = 0;
+    for (int e = srp[o]; e < srp[o + 1]; ++e) len += u_item[scol[e] + 1] - u_item[scol[e]];
+    max_len = std::max(max_len, len);
+  }
+  const int syn_lanes = c->tune_sp_syn_lanes ? c->tune_sp_syn_lanes : (max_len > 128 ? 32 : 16);
+  const int per = (max_len + syn_lanes - 1) / syn_lanes;        // entries per lane
+  const int syn_len = (per <= 8 ? per : (per + 3) / 4 * 4) * syn_lanes;
+  std::vector<int32_t> pad_col((size_t)syn_len * c->N, 0);
+  std::vector<double> pad_w((size_t)syn_len * c->N, 0.0);
+  for (int o = 0; o < c->N; ++o) {
+    size_t d = (size_t)o * syn_len;
+    for (int e = srp[o]; e < srp[o + 1]; ++e)
+      for (int it = u_item[scol[e]]; it < u_item[scol[e] + 1]; ++it) {
+        pad_col[d] = it;
+        pad_w[d++] = sw[e];
+      }
+  }
+  const int64_t nnz = csr.rowptr[c->N];
+  const size_t n1 = std::max<int64_t>(nnz, 1);
+  if ((s = dalloc(c, (void **)&c->sp_col, sizeof(uint32_t) * n1, "spatial columns")) != TLT_OK ||
+      (s = dalloc(c, &c->sp_val, c->esz * n1, "spatial values")) != TLT_OK ||
+      (s = dalloc(c, (void **)&c->sp_item_e, sizeof(int64_t) * item_e.size(), "spatial items")) != TLT_OK ||
+      (s = dalloc(c, (void **)&c->sp_syn_col, sizeof(int32_t) * pad_col.size(), "synthesis")) != TLT_OK ||
+      (s = dalloc(c, &c->sp_syn_w, c->esz * pad_w.size(), "synthesis")) != TLT_OK) {
+    free_spatial(c);
+    return s;
+  }
+  hipError_t e = hipSuccess;
+  if (nnz > 0) e = hipMemcpy(c->sp_col, csr.col.data(), sizeof(uint32_t) * nnz, hipMemcpyHostToDevice);
+  auto put = [&](void *dst, const std::vector<double> &v) {
+    if (c->fp64) return hipMemcpy(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice);
+    std::vector<float> f(v.begin(), v.end());
+    return hipMemcpy(dst, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice);
+  };
+  if (e == hipSuccess && nnz > 0) e = put(c->sp_val, csr.val);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->sp_item_e, item_e.data(), sizeof(int64_t) * item_e.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->sp_syn_col, pad_col.data(), sizeof(int32_t) * pad_col.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = put(c->sp_syn_w, pad_w);
+  if (e != hipSuccess) {
+    free_spatial(c);
+    return hip_fail(c, e, "load_spatial upload");
+  }
+  c->sp_items = n_items;
+  c->sp_syn_len = syn_len;
+  c->sp_syn_lanes = syn_lanes;
+  c->sp_mean_item = n_items > 0 ? (double)nnz / n_items : 0.0;
+  c->sp_nnz = nnz;
+  c->sp_levels = (int)csr.sizes.size();
+  for (int i = 0; i < c->sp_levels; ++i) c->sp_sizes[i] = csr.sizes[i];
+  c->sp_rowptr = std::move(csr.rowptr);
+  c->sp_nnz_k = std::move(csr.nnz_k);
+  c->sp_energy = std::move(csr.energy_kept);
+  c->spatial = true;
+  return TLT_OK;
+}
+
+tlt_status tlt_spatial_info(tlt_ctx *c, int64_t *nnz, int32_t *levels, int64_t *nnz_k,
+                            double *energy_kept) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->spatial) return fail(&c->err, TLT_E_STATE, "no spatial compression loaded");
+  if (nnz) *nnz = c->sp_nnz;
+  if (levels) *levels = c->sp_levels;
+  for (int k = 0; k < c->K; ++k) {
+    if (nnz_k) nnz_k[k] = c->sp_nnz_k[k];
+    if (energy_kept) energy_kept[k] = c->sp_energy[k];
+  }
+  return TLT_OK;
+}
+
+tlt_status tlt_read_spatial(tlt_ctx *c, int64_t u0, int64_t n_u, int64_t *rowptr_out,
+                            uint32_t *col_out, double *val_out, int64_t capacity) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->spatial) return fail(&c->err, TLT_E_STATE, "no spatial compression loaded");
+  if (u0 < 0 || n_u < 0 || u0 + n_u > c->N || !rowptr_out)
+    return fail(&c->err, TLT_E_ARG, "rows out of range");
+  const int64_t base = c->sp_rowptr[u0];
+  for (int64_t i = 0; i <= n_u; ++i) rowptr_out[i] = c->sp_rowptr[u0 + i] - base;
+  const int64_t m = rowptr_out[n_u];
+  if (m > capacity) return fail(&c->err, TLT_E_ARG, "capacity below the entries of these rows");
+  if (m == 0) return TLT_OK;
+  if (!col_out || !val_out) return fail(&c->err, TLT_E_ARG, "NULL output");
+  HIPC(c, hipDeviceSynchronize());
+  HIPC(c, hipMemcpy(col_out, c->sp_col + base, sizeof(uint32_t) * m, hipMemcpyDeviceToHost));
+  if (c->fp64) {
+    HIPC(c, hipMemcpy(val_out, (const double *)c->sp_val + base, sizeof(double) * m, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(m);
+    HIPC(c, hipMemcpy(f.data(), (const float *)c->sp_val + base, sizeof(float) * m, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < m; ++i) val_out[i] = f[i];
+  }
+  return TLT_OK;
+}
+
 tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
   if (!c->loaded) return fail(&c->err, TLT_E_STATE, "render before load_transport");
@@ -882,8 +1060,14 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (!B) return fail(&c->err, TLT_E_ARG, "B is NULL");
   if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
     return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
-  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING))
+  if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING |
+                TLT_SPATIAL))
     return fail(&c->err, TLT_E_ARG, "unknown flags");
+  const bool spatial = flags & TLT_SPATIAL;
+  if (spatial && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING)))
+    return fail(&c->err, TLT_E_ARG,
+                "TLT_SPATIAL excludes TLT_SAVE_FOR_BACKWARD, TLT_PLAIN_ROWS and TLT_FOLDED_LIGHTING");
+  if (spatial && !c->spatial) return fail(&c->err, TLT_E_STATE, "TLT_SPATIAL before load_spatial");
   if ((flags & TLT_FOLDED_LIGHTING) && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS)))
     return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING excludes TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS");
   if ((flags & TLT_FOLDED_LIGHTING) && c->use_E)
@@ -924,7 +1108,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     HIPC(c, launch_folded(c->P, c->Psh, c->n_sh, c->K, c->gcol, c->Cs, c->sh, cols, c->N, c->perm, B,
                           c->fp64, c->fold, st));
     c->v_valid = false;
-  } else if (!relight && c->V) {
+  } else if (!relight && c->V && !spatial) {
     // material-only edit: reuse the saved per-term transport v_k
     if (do_gk) {
       StageTimer t(c, 0, st);
@@ -944,8 +1128,9 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     a.partial = c->partial;
     a.ehat2 = c->ehat2;
     a.split = c->vdt == TLT_BF16 ? 1 : 2;
-    if (!use_tiles && (s = ensure_partition(c)) != TLT_OK) return s;
-    if (c->n_zero > 0 && !use_tiles) {
+    const bool rows_kernel = !use_tiles && !spatial;
+    if (rows_kernel && (s = ensure_partition(c)) != TLT_OK) return s;
+    if (c->n_zero > 0 && rows_kernel) {
       a.B = B;
       a.zero_v = c->zero_v;
       a.n_zero = c->n_zero;
@@ -955,9 +1140,41 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
       StageTimer t(c, 1, st);
       HIPC(c, launch_prep(a, st));
     }
+    SpatialArgs spa;
+    std::memset(&spa, 0, sizeof(spa));
     {
       StageTimer t(c, 2, st);
-      if (use_tiles) {
+      if (spatial) {
+        const size_t pb = c->esz * (size_t)std::max(c->sp_items, 1) * c->C;
+        if (c->sp_part_bytes < pb) {
+          dfree(c->sp_part);
+          c->sp_part_bytes = 0;
+          if ((s = dalloc(c, &c->sp_part, pb, "spatial partial sums")) != TLT_OK) return s;
+          c->sp_part_bytes = pb;
+        }
+        spa.col = c->sp_col;
+        spa.val = c->sp_val;
+        spa.n_items = c->sp_items;
+        // built-in shape: a wave per item, four entries per lane and pass
+        spa.lanes_per_item = c->tune_sp_lanes ? c->tune_sp_lanes : 64;
+        spa.unroll = c->tune_sp_unroll ? c->tune_sp_unroll : 4;
+        spa.item_e0 = c->sp_item_e;
+        spa.item_e1 = c->sp_item_e + c->sp_items;
+        spa.part = c->sp_part;
+        spa.syn_len = c->sp_syn_len;
+        spa.syn_lanes = c->sp_syn_lanes;
+        spa.syn_col = c->sp_syn_col;
+        spa.syn_w = c->sp_syn_w;
+        spa.ehat = c->ehat;
+        spa.gcol = c->gcol;
+        spa.Cs = c->Cs;
+        spa.C = c->C;
+        spa.K = c->K;
+        spa.N = c->N;
+        spa.perm = c->perm;
+        spa.B = B;
+        HIPC(c, launch_spatial_rows(spa, c->fp64, st));
+      } else if (use_tiles) {
         HIPC(c, launch_tiles(tile_args(c, c->ehat, c->ehat2, c->Cs, c->C, c->gcol, B,
                                        save ? c->V : nullptr, c->Cs),
                              c->vdt, st));
@@ -967,7 +1184,11 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
         HIPC(c, launch_stream(sa, c->vdt, c->fp64, c->cpl, st));
       }
     }
-    c->v_valid = save;
+    if (spatial) {
+      StageTimer t(c, 5, st);
+      HIPC(c, launch_spatial_synthesis(spa, c->fp64, st));
+    }
+    c->v_valid = save && !spatial;
   }
   c->mat_dirty = false;
   c->light_dirty = false;
@@ -1013,6 +1234,26 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
       if (value > 1) return fail(&c->err, TLT_E_ARG, "non-temporal flag must be 0 or 1");
       c->tune_stream_nt = value;
       break;
+    case TLT_TUNE_SPATIAL_LANES:
+      if (value != 0 && value != 16 && value != 32 && value != 64)
+        return fail(&c->err, TLT_E_ARG, "lanes per item must be 16, 32 or 64");
+      c->tune_sp_lanes = value;
+      break;
+    case TLT_TUNE_SPATIAL_UNROLL:
+      if (value != 0 && value != 4 && value != 8 && value != 16)
+        return fail(&c->err, TLT_E_ARG, "entries per lane must be 4, 8 or 16");
+      c->tune_sp_unroll = value;
+      break;
+    case TLT_TUNE_SPATIAL_SYNTH_LANES:
+      if (value != 0 && value != 8 && value != 16 && value != 32)
+        return fail(&c->err, TLT_E_ARG, "lanes per output position must be 8, 16 or 32");
+      c->tune_sp_syn_lanes = value;
+      break;
+    case TLT_TUNE_SPATIAL_SEGMENT:
+      if (value != 0 && (value < 64 || value > (1 << 20)))
+        return fail(&c->err, TLT_E_ARG, "segment length must be in 64 .. 2^20");
+      c->tune_sp_segment = value;
+      break;
     default: return fail(&c->err, TLT_E_ARG, "unknown tuning key");
   }
   return TLT_OK;
@@ -1023,7 +1264,7 @@ tlt_status tlt_profile_enable(tlt_ctx *c, int mode) {
   if (mode < 0 || mode > 2) return fail(&c->err, TLT_E_ARG, "mode must be 0, 1 or 2");
   if (mode == 1) {
     prof_drain(c);
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 6; ++i) {
       c->prof_ms[i] = 0.0;
       c->prof_n[i] = 0;
     }
@@ -1034,7 +1275,7 @@ tlt_status tlt_profile_enable(tlt_ctx *c, int mode) {
 
 tlt_status tlt_profile_read(tlt_ctx *c, int stage, double *total_ms, int64_t *launches) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
-  if (stage < 0 || stage > 4) return fail(&c->err, TLT_E_ARG, "stage must be in 0..4");
+  if (stage < 0 || stage > 5) return fail(&c->err, TLT_E_ARG, "stage must be in 0..5");
   prof_drain(c);
   if (total_ms) *total_ms = c->prof_ms[stage];
   if (launches) *launches = c->prof_n[stage];

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtlt.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 WAVELET_NONE, WAVELET_HAAR = 0, 1
-SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS, FOLDED_LIGHTING = 1, 2, 4, 8
+SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS, FOLDED_LIGHTING, SPATIAL = 1, 2, 4, 8, 16
 LAYOUTS = {"auto": 0, "rows": 1, "tiles": 2}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
@@ -65,6 +65,13 @@ class TransportDesc(ctypes.Structure):
     ]
 
 
+class SpatialDesc(ctypes.Structure):
+    _fields_ = [
+        ("energy", ctypes.c_double), ("levels", ctypes.c_int32), ("threads", ctypes.c_int32),
+        ("col", _i32p), ("val", _f64p),
+    ]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -90,6 +97,18 @@ _get_tile = _sig("tlt_get_tile", ctypes.c_int, _p)
 _version = _sig("tlt_version", ctypes.c_char_p)
 _set_tuning = _sig("tlt_set_tuning", ctypes.c_int, _p, ctypes.c_int32, ctypes.c_int32)
 _set_irradiance = _sig("set_irradiance", ctypes.c_int, _p, ctypes.c_int, _p)
+_spatial_rows = _sig("tlt_spatial_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                     ctypes.c_int64, _i32p, _f64p, ctypes.c_double, ctypes.c_int32,
+                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32), _f64p,
+                     ctypes.c_int64)
+_spatial_synthesis = _sig("tlt_spatial_synthesis", ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                          _i32p, _i32p, _f64p, ctypes.c_int64)
+_load_spatial = _sig("load_spatial", ctypes.c_int, _p, ctypes.POINTER(SpatialDesc))
+_spatial_info = _sig("tlt_spatial_info", ctypes.c_int, _p, ctypes.POINTER(ctypes.c_int64),
+                     _i32p, ctypes.POINTER(ctypes.c_int64), _f64p)
+_read_spatial = _sig("tlt_read_spatial", ctypes.c_int, _p, ctypes.c_int64, ctypes.c_int64,
+                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32), _f64p,
+                     ctypes.c_int64)
 _profile_enable = _sig("tlt_profile_enable", ctypes.c_int, _p, ctypes.c_int)
 _profile_read = _sig("tlt_profile_read", ctypes.c_int, _p, ctypes.c_int,
                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64))
@@ -100,11 +119,17 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
-            "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance"]
+            "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
+            "load_spatial", "tlt_spatial_info", "tlt_read_spatial", "tlt_spatial_rows",
+            "tlt_spatial_synthesis"]
 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
+TUNE_SPATIAL_LANES, TUNE_SPATIAL_UNROLL, TUNE_SPATIAL_SYNTH_LANES, TUNE_SPATIAL_SEGMENT = 5, 6, 7, 8
 TUNING_KEYS = {"tile_chunk": TUNE_TILE_CHUNK, "stream_waves_per_cu": TUNE_STREAM_WAVES_PER_CU,
-               "stream_epl": TUNE_STREAM_EPL, "stream_nt": TUNE_STREAM_NT}
+               "stream_epl": TUNE_STREAM_EPL, "stream_nt": TUNE_STREAM_NT,
+               "spatial_lanes": TUNE_SPATIAL_LANES, "spatial_unroll": TUNE_SPATIAL_UNROLL,
+               "spatial_synth_lanes": TUNE_SPATIAL_SYNTH_LANES,
+               "spatial_segment": TUNE_SPATIAL_SEGMENT}
 
 
 class TltError(RuntimeError):
@@ -189,6 +214,41 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def spatial_rows(col, val, n_cols, energy, levels=0):
+    """Host spatial compression of float64 Step-1 rows col/val [N, K, n_keep]
+    -> (rowptr [N+1], k, j, values) of the kept entries of Z over u."""
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    val = np.ascontiguousarray(val, dtype=np.float64)
+    N, K, n_keep = col.shape
+    rp = np.zeros(N + 1, np.int64)
+    st = _spatial_rows(N, n_cols, K, n_keep, _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double),
+                       float(energy), int(levels), _ptr(rp, ctypes.c_int64), None, None, 0)
+    m = int(rp[-1])
+    if st != OK and m == 0:
+        _check(st, None)
+    cw = np.zeros(max(m, 1), np.uint32)
+    v = np.zeros(max(m, 1), np.float64)
+    _check(_spatial_rows(N, n_cols, K, n_keep, _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double),
+                         float(energy), int(levels), _ptr(rp, ctypes.c_int64),
+                         _ptr(cw, ctypes.c_uint32), _ptr(v, ctypes.c_double), m), None)
+    return rp, (cw[:m] >> 24).astype(np.int64), (cw[:m] & 0xFFFFFF).astype(np.int64), v[:m]
+
+
+def spatial_synthesis(n, levels=0):
+    """w_1^{-1} over a list of n as CSR over the output position ->
+    (rowptr [n+1], coefficient index, weight)."""
+    rp = np.zeros(n + 1, np.int32)
+    st = _spatial_synthesis(n, levels, _ptr(rp, ctypes.c_int32), None, None, 0)
+    m = int(rp[-1])
+    if st != OK and m == 0:
+        _check(st, None)
+    col = np.zeros(max(m, 1), np.int32)
+    w = np.zeros(max(m, 1), np.float64)
+    _check(_spatial_synthesis(n, levels, _ptr(rp, ctypes.c_int32), _ptr(col, ctypes.c_int32),
+                              _ptr(w, ctypes.c_double), m), None)
+    return rp, col[:m].astype(np.int64), w[:m]
+
+
 class Renderer:
     """One library context holding one loaded transport.
 
@@ -263,6 +323,47 @@ class Renderer:
         self.loaded = True
         return self
 
+    # -- spatial compression ----------------------------------------------
+    def load_spatial(self, energy, levels=0, threads=0, scene=None, col=None, val=None):
+        """Spatially compresses the loaded transport (load_spatial); the
+        float64 Step-1 rows come from ``col``/``val`` [N, K, n_keep] or are
+        rebuilt on the host from ``scene`` (default: the loaded scene)."""
+        if col is None:
+            sc = self.scene if scene is None else scene
+            col, val = build_rows(sc, self.n_keep, "haar" if self.wavelet == WAVELET_HAAR else "none",
+                                  np.arange(self.N))
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        assert col.shape == (self.N, self.K, self.n_keep) and val.shape == col.shape
+        d = SpatialDesc()
+        d.energy, d.levels, d.threads = float(energy), int(levels), int(threads)
+        d.col = _ptr(col, ctypes.c_int32)
+        d.val = _ptr(val, ctypes.c_double)
+        return _check(_load_spatial(self._h, ctypes.byref(d)), self._h)
+
+    def spatial_info(self):
+        """(kept entries, levels, kept entries per term, retained energy per term)."""
+        nnz = ctypes.c_int64()
+        lv = ctypes.c_int32()
+        nk = np.zeros(self.K, np.int64)
+        ek = np.zeros(self.K, np.float64)
+        _check(_spatial_info(self._h, ctypes.byref(nnz), ctypes.byref(lv),
+                             _ptr(nk, ctypes.c_int64), _ptr(ek, ctypes.c_double)), self._h)
+        return nnz.value, lv.value, nk, ek
+
+    def read_spatial(self, u0=0, n_u=None):
+        """Kept entries of output coefficients u0 .. u0+n_u-1 ->
+        (rowptr [n_u+1], k, j, values)."""
+        n_u = self.N - u0 if n_u is None else n_u
+        rp = np.zeros(n_u + 1, np.int64)
+        _read_spatial(self._h, u0, n_u, _ptr(rp, ctypes.c_int64), None, None, 0)
+        m = int(rp[-1])
+        cw = np.zeros(max(m, 1), np.uint32)
+        v = np.zeros(max(m, 1), np.float64)
+        _check(_read_spatial(self._h, u0, n_u, _ptr(rp, ctypes.c_int64), _ptr(cw, ctypes.c_uint32),
+                             _ptr(v, ctypes.c_double), m), self._h)
+        return rp, (cw[:m] >> 24).astype(np.int64), (cw[:m] & 0xFFFFFF).astype(np.int64), v[:m]
+
     # -- inputs -----------------------------------------------------------
     def set_irradiance(self, E):
         """E: CUDA tensor [n_light, N, 3] (original vertex order; float64 for
@@ -302,13 +403,14 @@ class Renderer:
         import torch
         return torch.float64 if self.fp64 else torch.float32
 
-    def render(self, out=None, save=False, force=False, plain=False, folded=False):
+    def render(self, out=None, save=False, force=False, plain=False, folded=False, spatial=False):
         import torch
         if out is None:
             out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
                               device=self.torch_device)
         flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0) | \
-            (PLAIN_ROWS if plain else 0) | (FOLDED_LIGHTING if folded else 0)
+            (PLAIN_ROWS if plain else 0) | (FOLDED_LIGHTING if folded else 0) | \
+            (SPATIAL if spatial else 0)
         _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags), self._h)
         return out
 
@@ -363,7 +465,8 @@ class Renderer:
         buf, _ = self.read_state(2)
         return buf.view(np.float64).reshape(self.n_mat, 3, self.K, 3)
 
-    STAGES = {"weights": 0, "irradiance": 1, "transport": 2, "adjoint": 3, "combine": 4}
+    STAGES = {"weights": 0, "irradiance": 1, "transport": 2, "adjoint": 3, "combine": 4,
+              "inverse": 5}
 
     def profile(self, enable=True):
         """Clear the stage totals and enable timing (True), or pause it."""

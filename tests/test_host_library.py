@@ -111,3 +111,93 @@ def test_autotune_candidates_and_table():
         assert e["tile_vertices"] in autotune.vertex_candidates(K)
         assert e["tile_chunk"] in autotune.chunk_candidates(storage)
         assert e["key"] == key
+
+
+def _check_kept_sets(s, energy, lib_keys, lib_vals, scale):
+    """The library's kept set equals the oracle's except, possibly, entries
+    whose rank at the cut is decided by rounding: both sets must retain the
+    energy fraction, and any entry in one set only must be no larger than
+    every entry the other keeps (relative 1e-9)."""
+    ora = np.argwhere(s.keep)                                   # (k, u, j)
+    ora_keys = set(map(tuple, ora.tolist()))
+    lib = set(lib_keys)
+    only = lib ^ ora_keys
+    mags = {kk: abs(s.Z[kk]) for kk in only}
+    for kk, m in mags.items():
+        k = kk[0]
+        kept_min = np.abs(s.Z[k][s.keep[k]]).min()
+        assert m <= kept_min * (1 + 1e-9), (kk, m, kept_min)
+    assert len(only) <= 2 * s.Z.shape[0], len(only)
+    z = np.array([s.Z[k, u, j] for (k, u, j) in lib_keys])
+    np.testing.assert_allclose(lib_vals, z, rtol=0, atol=1e-12 * scale)
+    for k in range(s.Z.shape[0]):
+        tot = (s.Z[k] ** 2).sum()
+        got = sum(s.Z[kk] ** 2 for kk in lib if kk[0] == k)
+        assert got >= energy * tot * (1 - 1e-12) or energy >= 1.0
+
+
+@pytest.mark.parametrize("name,kw,energy", [
+    ("haar-f32-10242", dict(subdiv=2, keep=0.25), 0.97),
+    ("haar-f32-10242", dict(subdiv=2, keep=0.25), 1.0),
+    ("dense-f64-642", dict(subdiv=2), 0.95),
+    ("haar-f32-10242", dict(subdiv=3, keep=None), 0.98),
+], ids=["haar-162-0.97", "haar-162-all", "plain-162-0.95", "haar-642-0.98"])
+def test_spatial_rows_match_oracle(name, kw, energy):
+    """Host precompute Step 2 (Sec. 3.2) against the oracle: same CDF 9/7
+    coefficients and, up to rounding at the cut, the same kept sets."""
+    from oracle.spatial import Spatial
+    w = synth.get(name).with_(**kw)
+    if kw.get("keep", 0) is None:
+        w = w.with_(keep=64 / w.n_vertices)
+    sc = scene_for(w)
+    o = Scene(w)
+    s = Spatial(o, energy)
+    col, val = tlt.build_rows(sc, w.n_keep, w.wavelet, np.arange(w.n_vertices))
+    n_cols = w.n_pad if w.wavelet == "haar" else w.n_vertices
+    rp, k, j, v = tlt.spatial_rows(col, val, n_cols, energy)
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and rp[-1] == len(k)
+    u = np.repeat(np.arange(w.n_vertices), np.diff(rp))
+    # rows hold their entries in (k, j) order
+    key = k * n_cols + j
+    for a, b in zip(rp[:-1], rp[1:]):
+        assert np.all(np.diff(key[a:b]) > 0)
+    _check_kept_sets(s, energy, list(zip(k.tolist(), u.tolist(), j.tolist())), v,
+                     np.abs(s.Z).max())
+    if energy >= 1.0:
+        assert len(k) == int((s.Z != 0).sum())
+
+
+def test_spatial_rows_error_paths():
+    col = np.zeros((4, 1, 2), np.int32)
+    val = np.ones((4, 1, 2))
+    with pytest.raises(tlt.TltError):
+        tlt.spatial_rows(col, val, 4, 0.9)                     # fewer than 8 vertices
+    col = np.zeros((16, 1, 2), np.int32)
+    col[:, 0, 1] = 1
+    val = np.ones((16, 1, 2))
+    with pytest.raises(tlt.TltError):
+        tlt.spatial_rows(col, val, 16, 0.0)                    # energy outside (0, 1]
+    with pytest.raises(tlt.TltError):
+        tlt.spatial_rows(col, val, 16, 0.9, levels=5)          # too many levels for 16
+    bad = col.copy()
+    bad[3, 0, 0] = 99
+    with pytest.raises(tlt.TltError):
+        tlt.spatial_rows(bad, val, 16, 0.9)                    # column out of range
+    rp, k, j, v = tlt.spatial_rows(col, val, 16, 1.0, levels=1)
+    assert rp[-1] == len(v) > 0
+
+
+@pytest.mark.parametrize("n,levels", [(8, 0), (13, 0), (642, 0), (2562, 0), (1000, 3)])
+def test_spatial_synthesis_operator_is_the_oracle_inverse(n, levels):
+    """Step 5 of Sec. 4 as a sparse matrix: equals the oracle's exact inverse
+    of the CDF 9/7 analysis (a sparse solve per level), and keeps only the
+    structural non-zeros (a few tens per output)."""
+    from oracle import cdf97
+    rp, col, w = tlt.spatial_synthesis(n, levels)
+    assert rp[0] == 0 and rp[-1] == len(w)
+    M = np.zeros((n, n))
+    M[np.repeat(np.arange(n), np.diff(rp)), col] = w
+    ref = cdf97.inverse(np.eye(n), levels)
+    assert np.abs(M - ref).max() < 1e-13
+    assert np.all(np.abs(ref[M == 0]) < 1e-13)
+    assert np.diff(rp).max() <= 8 * (len(cdf97.band_sizes(n, levels)) + 2)
