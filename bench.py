@@ -361,6 +361,7 @@ def main():
                        else ("rows" if args.plain else "tiles")),
             "spatial": sp,
             "tile_shape": ({"tile_vertices": r.tuning["tile_vertices"], "tile_chunk": r.tuning["tile_chunk"],
+                            "wave_shape": r.tuning.get("tile_shape", 0) or "built-in",
                             "source": "autotuner table"} if getattr(r, "tuning", None) else "built-in"),
             "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),
             "stage_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stage_ms.items()},

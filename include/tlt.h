@@ -364,6 +364,11 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *   TLT_TUNE_STREAM_EPL          entries per lane and step of the row kernel
  *                                for narrow launches: 4, 8 or 16
  *   TLT_TUNE_STREAM_NT           1 = non-temporal loads of the rows
+ *   TLT_TUNE_TILE_SHAPE          16-bit tiles of 8 m-tiles: 100 MTW + 10 NT
+ *                                + IPT with MTW m-tiles per wave, NT
+ *                                16-column tiles per group and IPT staged
+ *                                items per thread: 231 (built-in), 241,
+ *                                432 or 442
  *   TLT_TUNE_SPATIAL_LANES       lanes per work item of the spatially
  *                                compressed transport: 16, 32 or 64
  *   TLT_TUNE_SPATIAL_UNROLL      its entries per lane and pass: 4, 8 or 16
@@ -384,7 +389,8 @@ enum {
   TLT_TUNE_SPATIAL_LANES = 5,
   TLT_TUNE_SPATIAL_UNROLL = 6,
   TLT_TUNE_SPATIAL_SYNTH_LANES = 7,
-  TLT_TUNE_SPATIAL_SEGMENT = 8
+  TLT_TUNE_SPATIAL_SEGMENT = 8,
+  TLT_TUNE_TILE_SHAPE = 9
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 

@@ -2,8 +2,10 @@
 
 For one workload it sweeps, on the GPU at hand, the tile block size (the
 vertices whose rows share one column union, which fixes both the bytes
-streamed per kept coefficient and the operand reuse) and the number of
-k-steps whose irradiance rows the tile kernel stages at once.  Each shape is
+streamed per kept coefficient and the operand reuse), the number of
+k-steps whose irradiance rows the tile kernel stages at once and, for
+16-bit blocks of 128 rows, the wave shape (m-tiles and column tiles per
+wave).  Each shape is
 timed with the library's own stage timing (transport kernel only, every
 stage recomputed), and the fastest is recorded in a table keyed by what
 fixes the kernel's shape: storage type, PCA terms, output columns, vertex
@@ -42,6 +44,12 @@ def vertex_candidates(K: int) -> list:
 def chunk_candidates(storage: str) -> list:
     """Caps on the staged k-steps (0 = as many as fit)."""
     return [0, 128, 64, 32] if storage == "f32" else [0, 8, 4]
+
+
+def shape_candidates(storage: str, rows: int) -> list:
+    """Wave shapes of 16-bit tiles with eight 16-row m-tiles (0 = built-in:
+    two m-tiles and three 16-column tiles per wave); other tiles have one."""
+    return [0, 241, 432] if storage != "f32" and rows == 128 else [0]
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -96,16 +104,21 @@ def tune(w, device: int = 0, steps: int = 64, log=print) -> dict:
                              layout="tiles", tile_vertices=V)
             r.set_lighting(L)
             r.set_material(th)
-            for kc in chunk_candidates(w.storage):
-                r.set_tuning("tile_chunk", kc)
-                us = _time_transport(r, B, steps)
-                results.append({"tile_vertices": V, "tile_chunk": kc, "transport_us": round(us, 2)})
-                log(f"[autotune] {w.name}: V={V} chunk={kc or 'max'}: {us:.1f} us")
+            for shape in shape_candidates(w.storage, V * w.K):
+                r.set_tuning("tile_shape", shape)
+                for kc in chunk_candidates(w.storage):
+                    r.set_tuning("tile_chunk", kc)
+                    us = _time_transport(r, B, steps)
+                    results.append({"tile_vertices": V, "tile_chunk": kc, "tile_shape": shape,
+                                    "transport_us": round(us, 2)})
+                    log(f"[autotune] {w.name}: V={V} shape={shape or 'built-in'} "
+                        f"chunk={kc or 'max'}: {us:.1f} us")
         finally:
             r.close()
     best = min(results, key=lambda e: e["transport_us"])
     return {"key": workload_key(w), "workload": w.name, "tile_vertices": best["tile_vertices"],
-            "tile_chunk": best["tile_chunk"], "transport_us": best["transport_us"],
+            "tile_chunk": best["tile_chunk"], "tile_shape": best["tile_shape"],
+            "transport_us": best["transport_us"],
             "device": torch.cuda.get_device_name(device), "steps": steps,
             "tuned": time.strftime("%Y-%m-%d"), "sweep": results}
 
@@ -126,7 +139,8 @@ def main(argv=None) -> int:
         e = tune(synth.get(name), steps=args.steps,
                  log=lambda *a: print(*a, file=sys.stderr, flush=True))
         table[e["key"]] = e
-        print(json.dumps({k: e[k] for k in ("key", "tile_vertices", "tile_chunk", "transport_us")}),
+        print(json.dumps({k: e[k] for k in ("key", "tile_vertices", "tile_chunk", "tile_shape",
+                                            "transport_us")}),
               flush=True)
     if args.write:
         with open(args.write, "w") as fh:

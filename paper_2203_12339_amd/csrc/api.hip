@@ -105,6 +105,7 @@ struct tlt_ctx {
 
   // tuning (tlt_set_tuning; 0 = built-in choice)
   int tune_tile_chunk = 0, tune_waves_per_cu = 0, tune_stream_epl = 0, tune_stream_nt = 0;
+  int tune_tile_shape = 0;
 
   // transport partition: n_waves equal row ranges; split vertices cleared
   int n_waves = 0;
@@ -365,6 +366,7 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   a.vsave = vsave;
   a.vs_stride = vs_stride;
   a.kc = c->tune_tile_chunk;
+  a.shape = c->tune_tile_shape;
   return a;
 }
 
@@ -1224,6 +1226,11 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
   if (value < 0) return fail(&c->err, TLT_E_ARG, "tuning values are >= 0 (0 = built-in choice)");
   switch (key) {
     case TLT_TUNE_TILE_CHUNK: c->tune_tile_chunk = value; break;
+    case TLT_TUNE_TILE_SHAPE:
+      if (value != 0 && value != 231 && value != 241 && value != 432 && value != 442)
+        return fail(&c->err, TLT_E_ARG, "tile shape must be 231, 241, 432 or 442");
+      c->tune_tile_shape = value;
+      break;
     case TLT_TUNE_STREAM_WAVES_PER_CU: c->tune_waves_per_cu = value; break;
     case TLT_TUNE_STREAM_EPL:
       if (value != 0 && value != 4 && value != 8 && value != 16)

@@ -449,6 +449,15 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
     return tiles_go<KIND, 1, 1, 16, 8, 16>(a, nt, st);
   } else {
     if (MT == 8) {
+      // tuned shapes: more m-tiles per wave halve the LDS reads of the
+      // staged irradiance per matrix instruction; four n-tiles per group
+      // cut the re-reads of W across column groups
+      switch (a.shape) {
+        case 241: return tiles_go<KIND, 2, 4, 4, 1>(a, nt, st);
+        case 432: return tiles_go<KIND, 4, 3, 4, 2>(a, nt, st);
+        case 442: return tiles_go<KIND, 4, 4, 4, 2>(a, nt, st);
+        default: break;
+      }
       if (ntw == 1) return tiles_go<KIND, 2, 1, 4, 1>(a, nt, st);
       if (ntw == 2) return tiles_go<KIND, 2, 2, 4, 1>(a, nt, st);
       return tiles_go<KIND, 2, 3, 4, 1>(a, nt, st);

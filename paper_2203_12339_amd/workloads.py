@@ -33,6 +33,7 @@ def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout=
                      tile_vertices=tile_vertices)
     if entry is not None:
         r.set_tuning("tile_chunk", entry["tile_chunk"])
+        r.set_tuning("tile_shape", entry.get("tile_shape", 0))
     r.scene = sc
     r.workload = w
     r.tuning = entry

@@ -399,6 +399,32 @@ def test_error_paths_on_device():
     r.close()
 
 
+@pytest.mark.parametrize("name,kw", [("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=16, n_cfg=16)),
+                                     ("large-f16-163842:shrunk-128rows",
+                                      dict(subdiv=4, n_light=2, n_cfg=1, sample_rows=0))],
+                         ids=["bf16", "f16"])
+def test_tile_wave_shapes_match_oracle(name, kw):
+    """Every wave shape the tuner may pick for 16-bit blocks of 128 rows
+    renders the oracle's result (C = 48 and 6 columns: full and partial
+    column groups)."""
+    from paper_2203_12339_amd import autotune
+    w = _workload(name, kw)
+    V = 128 // w.K
+    say(f"[shapes] {name}: V={V} C={3 * w.n_out}")
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ref = oracle_scene(w).render(L, th)
+    r = renderer_for(w, tile_vertices=V)
+    for shape in autotune.shape_candidates(w.storage, V * w.K):
+        for kc in autotune.chunk_candidates(w.storage):
+            r.set_tuning("tile_shape", shape)
+            r.set_tuning("tile_chunk", kc)
+            _, _, _, B = _render(w, L, th, renderer=r)
+            e = normwise(B, ref)
+            assert e <= TOL[w.storage], (shape, kc, e)
+    r.close()
+
+
 def test_autotune_sweeps_shapes_that_all_match_oracle():
     """The autotuner's sweep on a small workload, and every swept tile block
     size rendering the oracle's result."""

@@ -110,7 +110,10 @@ def test_autotune_candidates_and_table():
         assert storage in ("f32", "bf16", "f16")
         assert e["tile_vertices"] in autotune.vertex_candidates(K)
         assert e["tile_chunk"] in autotune.chunk_candidates(storage)
+        assert e.get("tile_shape", 0) in autotune.shape_candidates(storage, e["tile_vertices"] * K)
         assert e["key"] == key
+    assert autotune.shape_candidates("bf16", 128) == [0, 241, 432]
+    assert autotune.shape_candidates("f32", 128) == [0] and autotune.shape_candidates("f16", 112) == [0]
 
 
 def _check_kept_sets(s, energy, lib_keys, lib_vals, scale):
