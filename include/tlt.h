@@ -369,6 +369,11 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                16-column tiles per group and IPT staged
  *                                items per thread: 231 (built-in), 241,
  *                                432 or 442
+ *   TLT_TUNE_IRRADIANCE_HAAR     1 = compute Ehat per frame as the Haar
+ *                                transform of A o (T L); 0 (default) = as
+ *                                G L with G = H pad(A o T) formed once, for
+ *                                launches of at most 32 columns (equal up
+ *                                to float32 rounding)
  *   TLT_TUNE_SPATIAL_LANES       lanes per work item of the spatially
  *                                compressed transport: 16, 32 or 64
  *   TLT_TUNE_SPATIAL_UNROLL      its entries per lane and pass: 4, 8 or 16
@@ -390,7 +395,8 @@ enum {
   TLT_TUNE_SPATIAL_UNROLL = 6,
   TLT_TUNE_SPATIAL_SYNTH_LANES = 7,
   TLT_TUNE_SPATIAL_SEGMENT = 8,
-  TLT_TUNE_TILE_SHAPE = 9
+  TLT_TUNE_TILE_SHAPE = 9,
+  TLT_TUNE_IRRADIANCE_HAAR = 10
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 

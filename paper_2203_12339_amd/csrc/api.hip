@@ -48,6 +48,12 @@ struct tlt_ctx {
   double mat_range[6] = {0, 0, 0, 0, 0, 0};
   bool has_range = false;
 
+  // G = H pad(A o T) [n_rows][G_ld] (column lm: Haar of the area-weighted
+  // transfer column), so that Ehat = G L with no per-frame Haar levels
+  void *Gmat = nullptr, *Gpart = nullptr;
+  int G_ld = 0;
+  int tune_irr_haar = 0;   // 1: per-frame Haar of A o (T L) instead of G L
+
   // lighting-transfer product for the adjoint: P[k][o][Psh] = W_k G
   bool have_P = false;
   int Psh = 0, Gs = 0;
@@ -206,6 +212,9 @@ void free_spatial(tlt_ctx *c) {
 void free_all(tlt_ctx *c) {
   free_columns(c);
   free_spatial(c);
+  dfree(c->Gmat);
+  dfree(c->Gpart);
+  c->G_ld = 0;
   dfree(c->col);
   dfree(c->val);
   dfree(c->T);
@@ -391,6 +400,33 @@ tlt_status ensure_V(tlt_ctx *c) {
 }
 
 // G = Haar(pad(A o T)) and P = W G (per k), for the lighting gradient.
+// Builds G = H pad(A o T) once: the irradiance pass with identity lighting.
+tlt_status ensure_G(tlt_ctx *c, hipStream_t st) {
+  if (c->Gmat) return TLT_OK;
+  const int ld = round_up(c->n_sh, 16);
+  Cols ident{c->n_sh, 1, 1, 1};
+  PrepArgs a = prep_args(c, ld, ident);
+  tlt_status s;
+  if ((s = dalloc(c, &c->Gpart, c->esz * (size_t)a.n_chunks * ld, "G partials")) != TLT_OK) return s;
+  if ((s = dalloc(c, &c->Gmat, c->esz * (size_t)c->n_rows * ld, "G")) != TLT_OK) {
+    dfree(c->Gpart);
+    return s;
+  }
+  a.n_tl_blocks = a.n_chunks * (ld / 16);
+  a.sh = nullptr;
+  a.ehat = c->Gmat;
+  a.partial = c->Gpart;
+  a.ehat2 = nullptr;
+  const hipError_t he = launch_prep(a, st);
+  if (he != hipSuccess) {
+    dfree(c->Gmat);
+    dfree(c->Gpart);
+    return hip_fail(c, he, "building G = H (A o T)");
+  }
+  c->G_ld = ld;
+  return TLT_OK;
+}
+
 tlt_status ensure_P(tlt_ctx *c, hipStream_t st) {
   if (c->have_P) return TLT_OK;
   int cplP = 0;
@@ -1125,6 +1161,19 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
       a.perm = c->perm;
     } else {
       a.sh = c->sh;
+      if (c->wavelet == TLT_WAVELET_HAAR && !c->tune_irr_haar && c->Cs <= 32) {
+        // Ehat = G L: one matrix product per chunk, no Haar levels.  Each
+        // 16-column tile of a chunk reads the chunk's G rows (padded length,
+        // float32), so this pays only for narrow launches; wide ones keep
+        // the per-frame Haar of the compact transfer rows.
+        if ((s = ensure_G(c, st)) != TLT_OK) return s;
+        a.T = c->Gmat;
+        a.tdt = c->fp64 ? TLT_F64 : TLT_F32;
+        a.t_ld = c->G_ld;
+        a.t_rows = c->n_rows;
+        a.area = nullptr;
+        a.haar = 0;
+      }
     }
     a.ehat = c->ehat;
     a.partial = c->partial;
@@ -1226,6 +1275,10 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
   if (value < 0) return fail(&c->err, TLT_E_ARG, "tuning values are >= 0 (0 = built-in choice)");
   switch (key) {
     case TLT_TUNE_TILE_CHUNK: c->tune_tile_chunk = value; break;
+    case TLT_TUNE_IRRADIANCE_HAAR:
+      if (value > 1) return fail(&c->err, TLT_E_ARG, "irradiance flag must be 0 or 1");
+      c->tune_irr_haar = value;
+      break;
     case TLT_TUNE_TILE_SHAPE:
       if (value != 0 && value != 231 && value != 241 && value != 432 && value != 442)
         return fail(&c->err, TLT_E_ARG, "tile shape must be 231, 241, 432 or 442");

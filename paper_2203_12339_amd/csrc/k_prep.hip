@@ -166,7 +166,8 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   // (lighting columns of the tile), As [ch_rows] (areas)
   CT *x = reinterpret_cast<CT *>(smem);
   TT *Ts = reinterpret_cast<TT *>(x + TL_CH * TL_STRIDE);   // storage type, as in T
-  CT *Ls = reinterpret_cast<CT *>(Ts + ((size_t)a.ch_rows * a.n_sh + 15) / 16 * 16);
+  const int t_ld = a.t_ld ? a.t_ld : a.n_sh;               // row stride of T
+  CT *Ls = reinterpret_cast<CT *>(Ts + ((size_t)a.ch_rows * t_ld + 15) / 16 * 16);
   CT *As = Ls + (size_t)a.n_shp * 16;
   const int chunk = t % a.n_chunks;
   const int ctile = t / a.n_chunks;
@@ -181,7 +182,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   uint32_t *ehat2 = (uint32_t *)a.ehat2;
   CT *partial = (CT *)a.partial;
 
-  const int nr_e = max(0, min(a.ch_rows, a.N - i0));
+  const int nr_e = max(0, min(a.ch_rows, (a.t_rows ? a.t_rows : a.N) - i0));
   if (a.E != nullptr) {
     // supplied irradiance: E at the chunk's vertices (gathered through the
     // Morton permutation) times the area, in place of T L
@@ -205,10 +206,10 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   const int nr = nr_e;                                      // real vertices of the chunk
   if (a.E == nullptr) {
     constexpr int TSZ = sizeof(TT), VEC = 16 / TSZ, VPT = 8;
-    const int nel = nr * a.n_sh;                            // elements of the chunk
+    const int nel = nr * t_ld;                              // elements of the chunk
     const int nvec = (nel + VEC - 1) / VEC;
     const __amdgpu_buffer_rsrc_t trs = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)((const char *)T + (size_t)i0 * a.n_sh * TSZ), (short)0, nel * TSZ, 0x00020000);
+        (void *)((const char *)T + (size_t)i0 * t_ld * TSZ), (short)0, nel * TSZ, 0x00020000);
     for (int v0 = 0; v0 < nvec; v0 += 256 * VPT) {
       uint4 buf[VPT];
 #pragma unroll
@@ -237,7 +238,9 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
       }
       Ls[idx] = b;
     }
-    for (int idx = threadIdx.x; idx < a.ch_rows; idx += 256) As[idx] = idx < nr ? area[i0 + idx] : CT(0);
+    // no area: rows that carry it already (the folded G = H (A o T))
+    for (int idx = threadIdx.x; idx < a.ch_rows; idx += 256)
+      As[idx] = idx < nr ? (area ? area[i0 + idx] : CT(1)) : CT(0);
   }
   __syncthreads();
   if (a.E == nullptr && 64 * wave < a.ch_rows) {
@@ -252,7 +255,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
         const int lr = 64 * wave + 16 * u + li;
         // rows past the last vertex (zero padding) and columns past n_sh
         // were never staged: they contribute zeros
-        const CT av = (lr < nr && kc < a.n_sh) ? ld<TT, CT>(Ts, lr * a.n_sh + kc) : CT(0);
+        const CT av = (lr < nr && kc < a.n_sh) ? ld<TT, CT>(Ts, lr * t_ld + kc) : CT(0);
         acc[u] = mfma16(av, b, acc[u]);
       }
     }
@@ -370,7 +373,8 @@ size_t prep_lds_bytes(const PrepArgs &a) {
   size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // material weights
   if (a.n_tl_blocks > 0)
     s = std::max(s, esz * ((size_t)TL_CH * TL_STRIDE + (size_t)a.n_shp * 16 + (size_t)a.ch_rows) +
-                        ((size_t)a.ch_rows * a.n_sh + 15) / 16 * 16 * (a.tdt == 0 ? 8 : a.tdt == 1 ? 4 : 2));
+                        ((size_t)a.ch_rows * (a.t_ld ? a.t_ld : a.n_sh) + 15) / 16 * 16 *
+                            (a.tdt == 0 ? 8 : a.tdt == 1 ? 4 : 2));
   return s;
 }
 

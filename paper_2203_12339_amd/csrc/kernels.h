@@ -48,8 +48,10 @@ struct PrepArgs {
   void *gcol;              // [K][Cs] compute precision
   // irradiance E = T L and its Haar transform
   int n_tl_blocks;         // n_chunks * Cs/16, or 0
-  const void *T;           // [N][n_sh] storage tdt
+  const void *T;           // [N][t_ld] storage tdt
   int N, n_sh, n_shp;
+  int t_ld;                // row stride of T (0 = n_sh)
+  int t_rows;              // rows of T (0 = N)
   const void *sh;          // [n_light][n_sh][3] compute precision; nullptr = identity
   const void *E;           // or: irradiance [n_light][N][3] (original order), replaces T L
   const int32_t *perm;     // Morton position -> original vertex id (with E)

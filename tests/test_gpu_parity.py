@@ -258,6 +258,29 @@ def test_supplied_irradiance(name, kw):
     r.close()
 
 
+@pytest.mark.parametrize("name,kw", [("haar-f32-10242:small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
+                                     ("haar-f32-10242:10", dict(subdiv=3, n_light=10, n_cfg=1)),
+                                     ("haar-f32-10242", {})],
+                         ids=["ragged", "30-columns", "full"])
+def test_irradiance_forms_agree(name, kw):
+    """Ehat per frame as G L (G = H pad(A o T) formed once) and as the Haar
+    transform of A o (T L): both give the oracle's radiance."""
+    w = _workload(name, kw)
+    say(f"[irradiance-forms] {name}: N={w.n_vertices} C={3 * w.n_out}")
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ref = oracle_scene(w).render(L, th)
+    r = renderer_for(w)
+    out = {}
+    for flag in (0, 1):
+        r.set_tuning("irradiance_haar", flag)
+        _, _, _, B = _render(w, L, th, renderer=r)
+        out[flag] = B
+        assert normwise(B, ref) <= TOL[w.storage], flag
+    assert normwise(out[0], out[1]) <= 2e-6
+    r.close()
+
+
 def test_graph_replay_matches_eager():
     """A full render captured once as a HIP graph reads the lighting and
     material buffers at replay: each replay, with eager renders and in-place
