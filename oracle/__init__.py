@@ -20,6 +20,8 @@ in plain NumPy float64, following the paper:
 * ``adjoint``   -- FP64 adjoint of O-B and its finite-difference check.
 * ``cdf97``     -- the CDF 9/7 output-side transform w_1 and its inverse
                    (Sec. 3.2; 9/7 per Sec. 5), filters from their definition.
+* ``fresnel``   -- Fresnel transmittance and the outgoing factor
+                   (1/pi) F_t(eta, w_o) of Eq. (3) and (6).
 * ``spatial``   -- spatial compression of the truncated rows by an energy
                    threshold and its rendering form (Eq. 9, 10; precompute
                    Step 2 of Sec. 3.2; Steps 2, 4, 5 of Sec. 4).
