@@ -224,6 +224,20 @@ tlt_status set_lighting(tlt_ctx *ctx, int n_light, const void *sh_dev);
 tlt_status set_irradiance(tlt_ctx *ctx, int n_light, const void *E_dev);
 
 /*
+ * Outgoing Fresnel factor of Eq. (3) and the last line of Eq. (6): with a
+ * view set, render multiplies each radiance by (1/pi) F_t(eta, w_o), w_o the
+ * direction from the vertex to `eye`, eta the channel's index of refraction
+ * of the set's material, F_t = 1 - F_r the unpolarised Fresnel
+ * transmittance of a smooth boundary (air outside, eta inside); vertices
+ * seen from behind (n . w_o <= 0) get 0.  eye [3], position and normal
+ * [N][3] in Morton order (as tlt_prepare_scene writes them), host memory,
+ * mm; the cosines are computed here in float64.  eye == NULL removes the
+ * view.  render_backward with a view set returns TLT_E_STATE.
+ * TLT_E_STATE before load_transport; TLT_E_ARG for an eye on a vertex.
+ */
+tlt_status set_view(tlt_ctx *ctx, const double *eye, const double *position, const double *normal);
+
+/*
  * Renders B [n_out][N][3] (original vertex order, float64 for an F64
  * transport else float32) into caller-owned device memory on hip_stream.
  * Recomputes only what changed since the last render (a material change

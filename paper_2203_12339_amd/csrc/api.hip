@@ -59,6 +59,11 @@ struct tlt_ctx {
   int Psh = 0, Gs = 0;
   void *P = nullptr;
 
+  // view for the outgoing Fresnel factor (set_view): cos(w_o, n) per
+  // Morton position, compute precision
+  void *view_cos = nullptr;
+  bool view = false;
+
   // inputs of the next render
   const void *sh = nullptr;
   const void *E = nullptr;   // supplied irradiance (set_irradiance) instead of SH lighting
@@ -212,6 +217,8 @@ void free_spatial(tlt_ctx *c) {
 void free_all(tlt_ctx *c) {
   free_columns(c);
   free_spatial(c);
+  dfree(c->view_cos);
+  c->view = false;
   dfree(c->Gmat);
   dfree(c->Gpart);
   c->G_ld = 0;
@@ -954,6 +961,35 @@ tlt_status set_irradiance(tlt_ctx *c, int n_light, const void *E_dev) {
   return TLT_OK;
 }
 
+tlt_status set_view(tlt_ctx *c, const double *eye, const double *position, const double *normal) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_view before load_transport");
+  if (!eye) {
+    c->view = false;
+    return TLT_OK;
+  }
+  if (!position || !normal) return fail(&c->err, TLT_E_ARG, "need positions and normals");
+  HIPC(c, hipSetDevice(c->device));
+  std::vector<double> cs(c->N);
+  for (int o = 0; o < c->N; ++o) {
+    const double d0 = eye[0] - position[3 * (size_t)o], d1 = eye[1] - position[3 * (size_t)o + 1],
+                 d2 = eye[2] - position[3 * (size_t)o + 2];
+    const double len = std::sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    if (!(len > 0.0) || !std::isfinite(len)) return fail(&c->err, TLT_E_ARG, "eye on a vertex or not finite");
+    cs[o] = (normal[3 * (size_t)o] * d0 + normal[3 * (size_t)o + 1] * d1 + normal[3 * (size_t)o + 2] * d2) / len;
+  }
+  tlt_status s;
+  if (!c->view_cos && (s = dalloc(c, &c->view_cos, c->esz * c->N, "view cosines")) != TLT_OK) return s;
+  if (c->fp64) {
+    HIPC(c, hipMemcpy(c->view_cos, cs.data(), sizeof(double) * c->N, hipMemcpyHostToDevice));
+  } else {
+    std::vector<float> f(cs.begin(), cs.end());
+    HIPC(c, hipMemcpy(c->view_cos, f.data(), sizeof(float) * c->N, hipMemcpyHostToDevice));
+  }
+  c->view = true;
+  return TLT_OK;
+}
+
 tlt_status load_spatial(tlt_ctx *c, const tlt_spatial_desc *d) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
   if (!c->loaded) return fail(&c->err, TLT_E_STATE, "load_spatial before load_transport");
@@ -1241,6 +1277,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     }
     c->v_valid = save && !spatial;
   }
+  if (c->view) HIPC(c, launch_view(B, c->view_cos, c->theta, cols, c->N, c->perm, c->fp64, st));
   c->mat_dirty = false;
   c->light_dirty = false;
   return TLT_OK;
@@ -1253,6 +1290,8 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
                 "render_backward needs a render with TLT_SAVE_FOR_BACKWARD of the current inputs");
   if (c->use_E)
     return fail(&c->err, TLT_E_STATE, "render_backward needs SH lighting, not a supplied irradiance");
+  if (c->view)
+    return fail(&c->err, TLT_E_STATE, "render_backward is for the radiance without the view factor");
   if (!dB || !dSH || !dTheta) return fail(&c->err, TLT_E_ARG, "NULL gradient pointer");
   hipStream_t st = (hipStream_t)stream;
   const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->Cs, c->fp64);

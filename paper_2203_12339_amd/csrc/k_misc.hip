@@ -21,6 +21,46 @@ __global__ __launch_bounds__(256) void k_combine(const CT *__restrict__ V, int C
   B[((int64_t)q * N + perm[o]) * 3 + ch] = s;
 }
 
+// Outgoing Fresnel factor of Eq. (3)/(6): B[q][perm[o]][ch] *= (1/pi)
+// F_t(eta[mat(q)][ch], w_o(o)), from cos(w_o, n) per Morton position (0 or
+// less: seen from behind, factor 0).  Unpolarised dielectric transmittance,
+// air outside, index eta inside.
+template <typename CT>
+__global__ __launch_bounds__(256) void k_view(CT *__restrict__ B, const CT *__restrict__ cosv,
+                                              const double *__restrict__ theta, Cols cols, int N,
+                                              const int32_t *__restrict__ perm) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)cols.n_out * N * 3) return;
+  const int ch = (int)(t % 3);
+  const int64_t r = t / 3;
+  const int o = (int)(r % N), q = (int)(r / N);
+  const int m = cols.n_mat > 1 ? q : 0;
+  const CT eta = (CT)theta[((size_t)m * 3 + ch) * 3 + 2];
+  const CT c = cosv[o];
+  CT f = 0;
+  if (c > CT(0)) {
+    const CT cc = c < CT(1) ? c : CT(1);
+    const CT ct = sqrt(CT(1) - (CT(1) - cc * cc) / (eta * eta));
+    const CT rs = (cc - eta * ct) / (cc + eta * ct);
+    const CT rp = (eta * cc - ct) / (eta * cc + ct);
+    f = (CT(1) - CT(0.5) * (rs * rs + rp * rp)) * CT(0.31830988618379067154);
+  }
+  B[((int64_t)q * N + perm[o]) * 3 + ch] *= f;
+}
+
+hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols, int N,
+                       const int32_t *perm, bool fp64, hipStream_t st) {
+  const int64_t n = (int64_t)cols.n_out * N * 3;
+  const unsigned blocks = (unsigned)((n + 255) / 256);
+  if (fp64)
+    TLT_LAUNCH(k_view<double>, dim3(blocks), dim3(256), 0, st, (double *)B, (const double *)cosv, theta,
+               cols, N, perm);
+  else
+    TLT_LAUNCH(k_view<float>, dim3(blocks), dim3(256), 0, st, (float *)B, (const float *)cosv, theta,
+               cols, N, perm);
+  return hipGetLastError();
+}
+
 hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
                           const int32_t *perm, void *B, bool fp64, hipStream_t st) {
   const int64_t n = (int64_t)N * C;

@@ -113,6 +113,10 @@ struct TileArgs {
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
 
+// Outgoing Fresnel factor (1/pi) F_t(eta, w_o) applied to B in place.
+hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols, int N,
+                       const int32_t *perm, bool fp64, hipStream_t st);
+
 // Material-only update: B from saved v_k [K][N][Cs] and gcol.
 hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
                           const int32_t *perm, void *B, bool fp64, hipStream_t st);

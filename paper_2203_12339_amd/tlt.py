@@ -103,6 +103,7 @@ _spatial_rows = _sig("tlt_spatial_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_
                      ctypes.c_int64)
 _spatial_synthesis = _sig("tlt_spatial_synthesis", ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
                           _i32p, _i32p, _f64p, ctypes.c_int64)
+_set_view = _sig("set_view", ctypes.c_int, _p, _f64p, _f64p, _f64p)
 _load_spatial = _sig("load_spatial", ctypes.c_int, _p, ctypes.POINTER(SpatialDesc))
 _spatial_info = _sig("tlt_spatial_info", ctypes.c_int, _p, ctypes.POINTER(ctypes.c_int64),
                      _i32p, ctypes.POINTER(ctypes.c_int64), _f64p)
@@ -121,7 +122,7 @@ EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", 
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
             "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
             "load_spatial", "tlt_spatial_info", "tlt_read_spatial", "tlt_spatial_rows",
-            "tlt_spatial_synthesis"]
+            "tlt_spatial_synthesis", "set_view"]
 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
 TUNE_SPATIAL_LANES, TUNE_SPATIAL_UNROLL, TUNE_SPATIAL_SYNTH_LANES, TUNE_SPATIAL_SEGMENT = 5, 6, 7, 8
@@ -324,6 +325,20 @@ class Renderer:
         _check(_load_transport(self._h, ctypes.byref(d)), self._h)
         self.loaded = True
         return self
+
+    # -- view -------------------------------------------------------------
+    def set_view(self, eye, scene=None):
+        """Applies (1/pi) F_t(eta, w_o) toward ``eye`` (mm) in later renders;
+        None removes it.  Positions and normals from ``scene`` (default: the
+        loaded one)."""
+        if eye is None:
+            return _check(_set_view(self._h, None, None, None), self._h)
+        sc = self.scene if scene is None else scene
+        e = np.ascontiguousarray(eye, dtype=np.float64)
+        pos = np.ascontiguousarray(sc["position"], dtype=np.float64)
+        nrm = np.ascontiguousarray(sc["normal"], dtype=np.float64)
+        return _check(_set_view(self._h, _ptr(e, ctypes.c_double), _ptr(pos, ctypes.c_double),
+                                _ptr(nrm, ctypes.c_double)), self._h)
 
     # -- spatial compression ----------------------------------------------
     def load_spatial(self, energy, levels=0, threads=0, scene=None, col=None, val=None):

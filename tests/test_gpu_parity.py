@@ -281,6 +281,48 @@ def test_irradiance_forms_agree(name, kw):
     r.close()
 
 
+@pytest.mark.parametrize("name,kw", [("haar-f32-10242:642", dict(subdiv=3, n_light=2, n_cfg=2)),
+                                     ("dense-f64-642", {})], ids=["f32", "f64"])
+def test_view_factor(name, kw):
+    """The outgoing Fresnel factor (1/pi) F_t(eta, w_o) of Eq. (3)/(6) on every
+    render path: against the oracle's radiance times its factor, and as the
+    same factor on the transport, rows, folded and spatial paths."""
+    from oracle.fresnel import view_factor
+    w = _workload(name, kw)
+    say(f"[view] {name}: N={w.n_vertices}")
+    tol = TOL[w.storage]
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    eye = np.array([30.0, 10.0, -5.0])
+    sc = oracle_scene(w)
+    f = view_factor(sc, eye, th)
+    r = renderer_for(w)
+    r.set_lighting(dev_tensor(L, light_dtype(w)))
+    r.set_material(dev_tensor(th, "f64"))
+    modes = [dict()]
+    if w.storage != "f64":
+        r.load_spatial(0.98)
+        modes += [dict(plain=True), dict(folded=True), dict(spatial=True)]
+    for m in modes:
+        r.set_view(None)
+        B0 = r.render(force=True, **m).cpu().numpy()
+        r.set_view(eye)
+        B1 = r.render(force=True, **m).cpu().numpy()
+        assert np.all(B1[f == 0] == 0), m
+        e = normwise(B1, B0 * f)
+        say(f"[view] {name} {m or 'transport'}: vs factor x plain {e:.2e}")
+        assert e <= tol, (m, e)
+    B1 = r.render(force=True).cpu().numpy()
+    assert normwise(B1, sc.render(L, th) * f) <= tol
+    r.render(save=True, force=True)
+    with pytest.raises(tlt.TltError) as ei:
+        r.render_backward(torch.zeros((w.n_out, w.n_vertices, 3), device="cuda:0",
+                                      dtype=torch.float64 if w.storage == "f64" else torch.float32))
+    assert ei.value.status == -2
+    r.set_view(None)
+    r.close()
+
+
 def test_graph_replay_matches_eager():
     """A full render captured once as a HIP graph reads the lighting and
     material buffers at replay: each replay, with eager renders and in-place
