@@ -297,6 +297,7 @@ PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
   a.basis = c->basis;
   a.nr = c->nr;
   a.K = c->K;
+  a.gk_stage = (size_t)c->K * c->nr <= 4096;   // 32 KB of basis in LDS
   a.T = c->T;
   a.N = c->N;
   a.n_sh = c->n_sh;

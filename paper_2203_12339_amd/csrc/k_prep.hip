@@ -73,12 +73,19 @@ __device__ inline RdGrad rd_grad(double r, double sa, double ss, double eta) {
 }
 
 __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
-  // smem: q[4][nr] (R_d and its three partials on the nodes), red[4][K][4]
+  // smem: q[4][nr] (R_d and its three partials on the nodes), red[K][4],
+  // bs[K][nr] (the basis, staged once)
   double *q = smem;
   double *red = smem + 4 * (size_t)a.nr;
+  double *bs = red + 4 * (size_t)a.K;
   const int m = mc / 3, ch = mc % 3;
   const double sa = a.theta[mc * 3 + 0], ss = a.theta[mc * 3 + 1], eta = a.theta[mc * 3 + 2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the basis is read with one batch of loads, before the dipole work (when
+  // it fits the staging budget; else it is read from memory in place)
+  if (a.gk_stage)
+    for (int i = threadIdx.x; i < a.K * a.nr; i += 256) bs[i] = a.basis[i];
+  const double *bsrc = a.gk_stage ? bs : a.basis;
   for (int n = threadIdx.x; n < a.nr; n += 256) {
     const RdGrad g = rd_grad(a.rn[n], sa, ss, eta);
     q[n] = g.R;
@@ -87,31 +94,31 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
     q[3 * a.nr + n] = g.de;
   }
   __syncthreads();
-  // projections on b_k: per-thread partial sums over its nodes, one wave
-  // reduction, then a fixed-order sum over the four waves.
-  for (int k = 0; k < a.K; ++k) {
-    double p0 = 0, p1 = 0, p2 = 0, p3 = 0;
-    for (int n = threadIdx.x; n < a.nr; n += 256) {
-      const double b = a.basis[(size_t)k * a.nr + n];
-      p0 = fma(q[n], b, p0);
-      p1 = fma(q[a.nr + n], b, p1);
-      p2 = fma(q[2 * a.nr + n], b, p2);
-      p3 = fma(q[3 * a.nr + n], b, p3);
+  // projections on b_k (Sec. 2.2): wave w takes quantity w (R_d or one of
+  // its partials) for eight terms at a time; lanes sum over the nodes in a
+  // fixed order, then the eight wave sums run side by side
+  for (int k0 = 0; k0 < a.K; k0 += 8) {
+    double p[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) p[j] = 0.0;
+    for (int n = lane; n < a.nr; n += 64) {
+      const double qv = q[wave * a.nr + n];
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k0 + j < a.K) p[j] = fma(qv, bsrc[(size_t)(k0 + j) * a.nr + n], p[j]);
     }
-    p0 = wave_sum(p0);
-    p1 = wave_sum(p1);
-    p2 = wave_sum(p2);
-    p3 = wave_sum(p3);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) p[j] = wave_sum(p[j]);
     if (lane == 0) {
-      double *r = red + ((size_t)wave * a.K + k) * 4;
-      r[0] = p0; r[1] = p1; r[2] = p2; r[3] = p3;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (k0 + j < a.K) red[(size_t)(k0 + j) * 4 + wave] = p[j];
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < 4 * a.K; t += 256) {
     const int k = t / 4, qn = t % 4;
-    double acc = 0.0;
-    for (int w = 0; w < 4; ++w) acc += red[((size_t)w * a.K + k) * 4 + qn];
+    const double acc = red[t];
     if (qn == 0) {
       a.g64[(size_t)mc * a.K + k] = acc;
       for (int o = 0; o < a.cols.n_out; ++o) {
@@ -370,7 +377,8 @@ __global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
 
 size_t prep_lds_bytes(const PrepArgs &a) {
   const size_t esz = a.fp64 ? 8 : 4;
-  size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * 4 * (size_t)a.K);   // material weights
+  size_t s = sizeof(double) * (4 * (size_t)a.nr + 4 * (size_t)a.K +
+                               (a.gk_stage ? (size_t)a.K * a.nr : 0));             // weights
   if (a.n_tl_blocks > 0)
     s = std::max(s, esz * ((size_t)TL_CH * TL_STRIDE + (size_t)a.n_shp * 16 + (size_t)a.ch_rows) +
                         ((size_t)a.ch_rows * (a.t_ld ? a.t_ld : a.n_sh) + 15) / 16 * 16 *

@@ -44,6 +44,7 @@ struct PrepArgs {
   const double *rn;        // [nr]
   const double *basis;     // [K][nr]
   int nr, K;
+  int gk_stage;            // stage the basis in LDS (K * nr small enough)
   double *g64, *dg64;      // [n_mat][3][K], [n_mat][3][K][3]
   void *gcol;              // [K][Cs] compute precision
   // irradiance E = T L and its Haar transform
