@@ -157,7 +157,65 @@ def per_step_timing(args, r, step, B):
     return out
 
 
+_SCENE = None
+
+
+def _oracle_chunk(args):
+    L, th, rows = args
+    return _SCENE.render_vertices(L, th, rows, block=32)
+
+
+def oracle_all_cores_child(name, rows_path):
+    """Child process of the CPU baseline (no GPU in it): the same oracle on
+    the same sample, split over a fork pool of the host cores."""
+    global _SCENE
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synth
+    from oracle.transport import Scene
+    w = synth.get(name)
+    L, th = synth.make_lighting(w), synth.make_materials(w)
+    _SCENE = Scene(w)
+    rows = np.load(rows_path)
+    n = max(1, min(16, os.cpu_count() or 1))
+    chunks = [c for c in np.array_split(rows, 4 * n) if len(c)]
+    with mp.get_context("fork").Pool(n) as pool:
+        pool.map(_oracle_chunk, [(L, th, chunks[0][:1])] * n)        # workers up
+        t0 = time.perf_counter()
+        pool.map(_oracle_chunk, [(L, th, c) for c in chunks])
+        dt = time.perf_counter() - t0
+    print(json.dumps({"value": round(len(rows) * w.n_out / dt, 3), "cores": n,
+                      "seconds": round(dt, 2)}), flush=True)
+
+
+def cpu_all_cores(w, rows):
+    """Runs oracle_all_cores_child in a fresh interpreter (this process holds
+    the GPU; the child never touches it) -> dict or None."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    with tempfile.TemporaryDirectory(dir="/tmp") as d:
+        path = os.path.join(d, "rows.npy")
+        np.save(path, np.asarray(rows))
+        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        try:
+            out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-all-cores",
+                                  w.name, path], capture_output=True, text=True, timeout=300, env=env)
+        except subprocess.TimeoutExpired:
+            return None
+        if out.returncode != 0:
+            log(f"[bench] all-cores oracle failed: {out.stderr[-300:]}")
+            return None
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+
 def main():
+    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-all-cores":
+        oracle_all_cores_child(sys.argv[2], sys.argv[3])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -338,6 +396,11 @@ def main():
                "sample": f"{len(rows)} seeded output vertices x {w.n_out} configs of {w.name}, "
                          f"O-B float64 (row precompute + transport), 1 thread, {dt:.1f}s"}
         log(f"[bench] oracle {cpu['value']} vertices/s; GPU rel err on sample {rel_err:.3e}")
+        allc = cpu_all_cores(w, rows)
+        if allc is not None:
+            cpu["all_cores"] = {"value": allc["value"], "unit": "vertices/s", "cores": allc["cores"],
+                                "sample": "the same vertices, a fork pool of one-thread workers"}
+            log(f"[bench] oracle on {allc['cores']} cores: {allc['value']} vertices/s")
 
     out = {
         "metric": "shaded vertices/sec (K-term wavelet transport) at stated rel. err; % HBM peak",
