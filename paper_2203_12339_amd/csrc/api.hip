@@ -95,7 +95,7 @@ struct tlt_ctx {
   size_t t_val_bytes = 0;
 
   // spatially compressed transport (load_spatial): CSR of the kept entries
-  // of Z_k = w_1 W_k^S over u, as work items of at most 1024 entries
+  // of Z_k = w_1 W_k^S over u, as work items of at most 2048 entries
   bool spatial = false;
   int sp_levels = 0, sp_sizes[32] = {0};
   int64_t sp_nnz = 0;
@@ -1004,7 +1004,7 @@ tlt_status load_spatial(tlt_ctx *c, const tlt_spatial_desc *d) {
                                d->levels, d->threads > 0 ? d->threads : (int)hw, csr, &c->err);
   if (s != TLT_OK) return s;
   // work items of at most SEG entries: a longer row is cut into consecutive items
-  const int64_t SEG = c->tune_sp_segment ? c->tune_sp_segment : 1024;
+  const int64_t SEG = c->tune_sp_segment ? c->tune_sp_segment : 2048;
   std::vector<int64_t> item_e;
   std::vector<int32_t> u_item((size_t)c->N + 1, 0);
   {
@@ -1025,7 +1025,7 @@ tlt_status load_spatial(tlt_ctx *c, const tlt_spatial_desc *d) {
   const int n_items = u_item[c->N];
   // w_1^{-1} (Step 5) as a sparse matrix, expanded over the work items of
   // each coefficient's row and stored as padded CSR rows: lanes per output
-  // position (tuning, else 16 or 32 by the longest row), rows padded to a
+  // position (tuning, else 32), rows padded to a
   // whole number of entries per lane (a multiple of 4 beyond 8)
   std::vector<int32_t> srp, scol;
   std::vector<double> sw;
@@ -1036,7 +1036,7 @@ tlt_status load_spatial(tlt_ctx *c, const tlt_spatial_desc *d) {
     for (int e = srp[o]; e < srp[o + 1]; ++e) len += u_item[scol[e] + 1] - u_item[scol[e]];
     max_len = std::max(max_len, len);
   }
-  const int syn_lanes = c->tune_sp_syn_lanes ? c->tune_sp_syn_lanes : (max_len > 128 ? 32 : 16);
+  const int syn_lanes = c->tune_sp_syn_lanes ? c->tune_sp_syn_lanes : 32;
   const int per = (max_len + syn_lanes - 1) / syn_lanes;        // entries per lane
   const int syn_len = (per <= 8 ? per : (per + 3) / 4 * 4) * syn_lanes;
   std::vector<int32_t> pad_col((size_t)syn_len * c->N, 0);
@@ -1243,9 +1243,10 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
         spa.col = c->sp_col;
         spa.val = c->sp_val;
         spa.n_items = c->sp_items;
-        // built-in shape: a wave per item, four entries per lane and pass
+        // built-in shape (measured at haar-f32-10242): a wave per item of at
+        // most 2048 entries, eight entries per lane and pass
         spa.lanes_per_item = c->tune_sp_lanes ? c->tune_sp_lanes : 64;
-        spa.unroll = c->tune_sp_unroll ? c->tune_sp_unroll : 4;
+        spa.unroll = c->tune_sp_unroll ? c->tune_sp_unroll : 8;
         spa.item_e0 = c->sp_item_e;
         spa.item_e1 = c->sp_item_e + c->sp_items;
         spa.part = c->sp_part;
