@@ -94,6 +94,36 @@ def _quantiles(ms):
             "p90_ms": round(float(np.percentile(a, 90)), 5), "n": int(a.size)}
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Reference HBM rates on this machine with library kernels, timed with
+    events: a device copy of `mib` MiB (read + write counted) and a sum over
+    it (read only); (copy GB/s, read GB/s)."""
+    import torch
+    src = torch.empty(mib << 18, dtype=torch.float32, device="cuda:0")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    sink = torch.empty((), dtype=torch.float32, device="cuda:0")
+    dst.copy_(src)
+    torch.sum(src, dim=0, out=sink)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    copy = 2 * (mib << 20) / timed(lambda: dst.copy_(src)) / 1e9
+    read = (mib << 20) / timed(lambda: torch.sum(src, dim=0, out=sink)) / 1e9
+    del src, dst
+    torch.cuda.synchronize()
+    log(f"[bench] {mib} MiB: device copy {copy:.0f} GB/s (read + write), sum {read:.0f} GB/s (read)")
+    return copy, read
+
+
 def per_step_timing(args, r, step, B):
     """Per-step time distributions, each step bracketed by events on the
     launch stream: warm (back to back), cold (a read of a scratch buffer evicts the
@@ -341,6 +371,7 @@ def main():
         + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in stage_ms.items()))
 
     timing = per_step_timing(args, r, step, B) if args.dist_steps > 0 else None
+    copy_gbs = copy_bandwidth() if args.dist_steps > 0 else None
 
     # roofline of the dominant kernel (the transport)
     C = 3 * w.n_out
@@ -372,6 +403,9 @@ def main():
                 "traffic": traffic, "kernel": kernel,
                 "kernel_us": round(avg_s * 1e6, 2), "kernel_launches_timed": n_tr,
                 "algorithmic_bytes": alg_bytes}
+    if copy_gbs:
+        roofline["reference_GBps"] = {"copy": round(copy_gbs[0], 1), "read": round(copy_gbs[1], 1),
+                                      "source": "torch copy_ and sum over 1 GiB on this GPU"}
     if timing and "transport_us" in timing.get("cold", {}):
         cold_s = timing["cold"]["transport_us"] * 1e-6
         roofline["cold"] = {"kernel_us": timing["cold"]["transport_us"],

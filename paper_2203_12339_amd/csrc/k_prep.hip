@@ -81,17 +81,36 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
   const int m = mc / 3, ch = mc % 3;
   const double sa = a.theta[mc * 3 + 0], ss = a.theta[mc * 3 + 1], eta = a.theta[mc * 3 + 2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // the basis is read with one batch of loads, before the dipole work (when
-  // it fits the staging budget; else it is read from memory in place)
-  if (a.gk_stage)
-    for (int i = threadIdx.x; i < a.K * a.nr; i += 256) bs[i] = a.basis[i];
+  // the basis is staged in LDS when it fits the budget (else it is read from
+  // memory in place).  With one node per thread (n_r <= 256, K <= 16) the
+  // thread's basis values are loaded into registers first and stored after
+  // the dipole work, so the loads complete under it.
   const double *bsrc = a.gk_stage ? bs : a.basis;
-  for (int n = threadIdx.x; n < a.nr; n += 256) {
-    const RdGrad g = rd_grad(a.rn[n], sa, ss, eta);
-    q[n] = g.R;
-    q[a.nr + n] = g.da;
-    q[2 * a.nr + n] = g.ds;
-    q[3 * a.nr + n] = g.de;
+  if (a.gk_stage && a.nr <= 256 && a.K <= 16) {
+    const int n = threadIdx.x;
+    double breg[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) breg[k] = (k < a.K && n < a.nr) ? a.basis[(size_t)k * a.nr + n] : 0.0;
+    if (n < a.nr) {
+      const RdGrad g = rd_grad(a.rn[n], sa, ss, eta);
+      q[n] = g.R;
+      q[a.nr + n] = g.da;
+      q[2 * a.nr + n] = g.ds;
+      q[3 * a.nr + n] = g.de;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k < a.K && n < a.nr) bs[(size_t)k * a.nr + n] = breg[k];
+  } else {
+    if (a.gk_stage)
+      for (int i = threadIdx.x; i < a.K * a.nr; i += 256) bs[i] = a.basis[i];
+    for (int n = threadIdx.x; n < a.nr; n += 256) {
+      const RdGrad g = rd_grad(a.rn[n], sa, ss, eta);
+      q[n] = g.R;
+      q[a.nr + n] = g.da;
+      q[2 * a.nr + n] = g.ds;
+      q[3 * a.nr + n] = g.de;
+    }
   }
   __syncthreads();
   // projections on b_k (Sec. 2.2): wave w takes quantity w (R_d or one of
