@@ -143,7 +143,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   for (int i = threadIdx.x; i < n_steps * KS; i += nthr) uc[i] = ucol[i];
   constexpr int QW = KIND == 0 ? 1 : 4;  // columns per item
   const int cq = (cg + QW - 1) / QW;     // items per (step, lane group)
-  int it_sl[IPT], it_eoff[IPT], it_col[IPT], it_lds[IPT];
+  int it_sl[IPT], it_eoff[IPT], it_col[IPT], it_lds[IPT], it_slot[IPT], it_sw[IPT];
 #pragma unroll
   for (int it = 0; it < IPT; ++it) {
     const int item = threadIdx.x + it * nthr;
@@ -157,7 +157,13 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     if constexpr (KIND == 0)
       it_lds[it] = (sl * 4 + lg) * CGS + n;
     else
-      it_lds[it] = ((sl * NT + n / 16) * H * 64 + lg * 16 + (n % 16)) * KPL;
+    {
+      // fragment base, lane slot of the first of the item's four columns,
+      // and the slot swizzle of this (column tile, lane group): see read_b
+      it_lds[it] = (sl * NT + n / 16) * H * 64 * KPL;
+      it_slot[it] = lg * 16 + (n % 16);
+      it_sw[it] = (n / 16 + NT * lg) & 3;
+    }
   }
   __syncthreads();  // union ids visible
   typedef typename std::conditional<KIND == 0, float, uint4>::type GT;
@@ -194,8 +200,9 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
               hw[i] = __builtin_amdgcn_perm(w1, w0, 0x05040100u);
               lw[i] = __builtin_amdgcn_perm(w1, w0, 0x07060302u);
             }
-            *reinterpret_cast<BFrag *>(stage + it_lds[it] + jj * KPL) = __builtin_bit_cast(BFrag, hw);
-            *reinterpret_cast<BFrag *>(stage + it_lds[it] + jj * KPL + 64 * KPL) =
+            const int ph = ((it_slot[it] + jj) ^ it_sw[it]) * KPL;
+            *reinterpret_cast<BFrag *>(stage + it_lds[it] + ph) = __builtin_bit_cast(BFrag, hw);
+            *reinterpret_cast<BFrag *>(stage + it_lds[it] + ph + 64 * KPL) =
                 __builtin_bit_cast(BFrag, lw);
           }
         }
@@ -229,7 +236,14 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
     for (int m = 0; m < MTW; ++m) dst[m] = TK::frag(wrs, loff[m], s * step_bytes);
   };
-  // B fragments of step sl of the staged chunk (unconditional LDS reads)
+  // B fragments of step sl of the staged chunk (unconditional LDS reads).
+  // 16-bit kinds: the fragment of (step, column tile nt, half h) holds lane
+  // l's 16 bytes at slot l ^ ((nt + NT (l / 16)) & 3).  The swizzle only
+  // permutes slots inside a group of four, so a quarter-wave still reads 16
+  // distinct 16-byte bank groups, and the staging writes -- each thread
+  // writes one column quad (four consecutive slots, one store each) for
+  // consecutive (column tile, lane group) pairs -- now spread a store
+  // instruction over all 16 bank groups instead of 4 of them.
   auto read_b = [&](int sl, BFrag (&dst)[NT][H]) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
@@ -240,8 +254,9 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
           const float v = stage[((size_t)sl * 4 + (lane >> 4)) * CGS + min(n, cg - 1)];
           dst[nt][h] = n < cg ? v : 0.f;
         } else {
+          const int slot = lane ^ ((nt + NT * (lane >> 4)) & 3);
           dst[nt][h] = *reinterpret_cast<const BFrag *>(
-              stage + ((size_t)((sl * NT + nt) * H + h) * 64 + lane) * KPL);
+              stage + ((size_t)((sl * NT + nt) * H + h) * 64 + slot) * KPL);
         }
       }
   };
