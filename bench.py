@@ -97,8 +97,11 @@ def _quantiles(ms):
 def copy_bandwidth(mib=1024, reps=10):
     """Reference HBM rates on this machine with library kernels, timed with
     events: a device copy of `mib` MiB (read + write counted) and a sum over
-    it (read only); (copy GB/s, read GB/s)."""
+    it (read only), and a read of it with the transport's 16-byte buffer loads
+    (the library's read probe, best of three grid sizes); (copy, read, probe)
+    in GB/s."""
     import torch
+    from paper_2203_12339_amd import tlt
     src = torch.empty(mib << 18, dtype=torch.float32, device="cuda:0")
     src.fill_(1.0)
     dst = torch.empty_like(src)
@@ -118,10 +121,16 @@ def copy_bandwidth(mib=1024, reps=10):
 
     copy = 2 * (mib << 20) / timed(lambda: dst.copy_(src)) / 1e9
     read = (mib << 20) / timed(lambda: torch.sum(src, dim=0, out=sink)) / 1e9
-    del src, dst
+    folds = torch.empty(4096 * 4, dtype=torch.int32, device="cuda:0")
+    own = 0.0
+    for blocks in (1024, 2048, 4096):
+        tlt.read_probe(src, folds, blocks)
+        own = max(own, (mib << 20) / timed(lambda: tlt.read_probe(src, folds, blocks)) / 1e9)
+    del src, dst, folds
     torch.cuda.synchronize()
-    log(f"[bench] {mib} MiB: device copy {copy:.0f} GB/s (read + write), sum {read:.0f} GB/s (read)")
-    return copy, read
+    log(f"[bench] {mib} MiB: device copy {copy:.0f} GB/s (read + write), sum {read:.0f} GB/s (read), "
+        f"16-byte buffer-load read {own:.0f} GB/s")
+    return copy, read, own
 
 
 def per_step_timing(args, r, step, B):
@@ -405,7 +414,9 @@ def main():
                 "algorithmic_bytes": alg_bytes}
     if copy_gbs:
         roofline["reference_GBps"] = {"copy": round(copy_gbs[0], 1), "read": round(copy_gbs[1], 1),
-                                      "source": "torch copy_ and sum over 1 GiB on this GPU"}
+                                      "buffer_load_read": round(copy_gbs[2], 1),
+                                      "source": "torch copy_ and sum, and the library's read "
+                                                "probe, over 1 GiB on this GPU"}
     if timing and "transport_us" in timing.get("cold", {}):
         cold_s = timing["cold"]["transport_us"] * 1e-6
         roofline["cold"] = {"kernel_us": timing["cold"]["transport_us"],

@@ -429,6 +429,17 @@ tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
  * TLT_E_ARG for another mode.  Do not enable during HIP graph capture.
  */
 tlt_status tlt_profile_enable(tlt_ctx *ctx, int mode);
+
+/*
+ * Measurement only: reads `bytes` of device buffer `buf` once, with the
+ * same 16-byte buffer loads the transport streams with (sixteen in flight
+ * per lane), split over `blocks` workgroups of 256 threads; each wave
+ * writes one folded word to out [blocks * 4] (device memory).  Timing it
+ * gives the read bandwidth this load path reaches on the GPU.  Each
+ * workgroup's share must stay below 1.75 GiB; `bytes` is a multiple of 16
+ * (zero allowed, then `buf` may be null).  TLT_E_ARG for bad arguments.
+ */
+tlt_status tlt_read_probe(const void *buf, int64_t bytes, uint32_t *out, int blocks, void *stream);
 tlt_status tlt_profile_read(tlt_ctx *ctx, int stage, double *total_ms, int64_t *launches);
 
 /* Library version string (static storage). */

@@ -1360,6 +1360,14 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
   return TLT_OK;
 }
 
+tlt_status tlt_read_probe(const void *buf, int64_t bytes, uint32_t *out, int blocks, void *stream) {
+  if ((!buf && bytes > 0) || !out || bytes < 0 || bytes % 16 || blocks < 1)
+    return fail(nullptr, TLT_E_ARG, "bad arguments");
+  const hipError_t e = launch_read_probe(buf, bytes, out, blocks, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, TLT_E_HIP, std::string("read probe: ") + hipGetErrorString(e));
+  return TLT_OK;
+}
+
 tlt_status tlt_profile_enable(tlt_ctx *c, int mode) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
   if (mode < 0 || mode > 2) return fail(&c->err, TLT_E_ARG, "mode must be 0, 1 or 2");

@@ -685,6 +685,43 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
 }
 
 // ---------------------------------------------------------------------------
+// Read-bandwidth probe (measurement only): every workgroup streams its
+// share of a buffer with 16-byte buffer loads, sixteen in flight per lane,
+// and folds the words into one value it writes out (so the loads are not
+// dropped).  Reads past the end return zeros.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_read_probe(const void *__restrict__ buf, int64_t bytes,
+                                                    uint32_t *__restrict__ out) {
+  const int64_t per = (bytes + gridDim.x - 1) / gridDim.x;
+  const int64_t begin = (per + 4095) / 4096 * 4096 * blockIdx.x;
+  const int64_t end = min(bytes, begin + (per + 4095) / 4096 * 4096);
+  uint32_t acc = 0;
+  if (begin < end) {
+    const int64_t len = end - begin;
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)((const char *)buf + begin), (short)0, (int)min<int64_t>(len, 0x7fffffff), 0x00020000);
+    for (int64_t off = 0; off < len; off += 16 * 256 * 16) {
+      uint4 v[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        v[u] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                             r, (int)(off + (u * 256 + threadIdx.x) * 16), 0, 0));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc ^= v[u].x + v[u].y + v[u].z + v[u].w;
+    }
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) out[blockIdx.x * 4 + (threadIdx.x >> 6)] = acc;
+}
+
+hipError_t launch_read_probe(const void *buf, int64_t bytes, uint32_t *out, int blocks, hipStream_t st) {
+  if (blocks < 1 || bytes < 0 || (bytes + blocks - 1) / blocks > 0x70000000) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_read_probe, dim3(blocks), dim3(256), 0, st, buf, bytes, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Storage conversion (load time): float64 -> float64/float32/bf16/f16, each
 // rounded to nearest even (16-bit types via float32).
 // ---------------------------------------------------------------------------

@@ -185,6 +185,9 @@ struct TileBuildArgs {
 hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st);
 hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st);
 
+// Read-bandwidth probe: streams `bytes` of buf; out [blocks * 4].
+hipError_t launch_read_probe(const void *buf, int64_t bytes, uint32_t *out, int blocks, hipStream_t st);
+
 // Storage conversion of float64 values to device storage type.
 hipError_t launch_quantize(const double *src, void *dst, int vdt, int64_t n, hipStream_t st);
 

@@ -104,6 +104,7 @@ _spatial_rows = _sig("tlt_spatial_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_
 _spatial_synthesis = _sig("tlt_spatial_synthesis", ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
                           _i32p, _i32p, _f64p, ctypes.c_int64)
 _set_view = _sig("set_view", ctypes.c_int, _p, _f64p, _f64p, _f64p)
+_read_probe = _sig("tlt_read_probe", ctypes.c_int, _p, ctypes.c_int64, _p, ctypes.c_int, _p)
 _load_spatial = _sig("load_spatial", ctypes.c_int, _p, ctypes.POINTER(SpatialDesc))
 _spatial_info = _sig("tlt_spatial_info", ctypes.c_int, _p, ctypes.POINTER(ctypes.c_int64),
                      _i32p, ctypes.POINTER(ctypes.c_int64), _f64p)
@@ -122,7 +123,7 @@ EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", 
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
             "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
             "load_spatial", "tlt_spatial_info", "tlt_read_spatial", "tlt_spatial_rows",
-            "tlt_spatial_synthesis", "set_view"]
+            "tlt_spatial_synthesis", "set_view", "tlt_read_probe"]
 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
 TUNE_SPATIAL_LANES, TUNE_SPATIAL_UNROLL, TUNE_SPATIAL_SYNTH_LANES, TUNE_SPATIAL_SEGMENT = 5, 6, 7, 8
@@ -235,6 +236,14 @@ def spatial_rows(col, val, n_cols, energy, levels=0):
                          float(energy), int(levels), _ptr(rp, ctypes.c_int64),
                          _ptr(cw, ctypes.c_uint32), _ptr(v, ctypes.c_double), m), None)
     return rp, (cw[:m] >> 24).astype(np.int64), (cw[:m] & 0xFFFFFF).astype(np.int64), v[:m]
+
+
+def read_probe(buf, out, blocks):
+    """Streams the CUDA tensor ``buf`` once (measurement of the read rate);
+    ``out``: int32 CUDA tensor of at least blocks * 4 elements."""
+    assert buf.is_cuda and out.is_cuda and out.numel() >= blocks * 4
+    _check(_read_probe(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size(),
+                       ctypes.c_void_p(out.data_ptr()), blocks, _stream()), None)
 
 
 def spatial_synthesis(n, levels=0):
