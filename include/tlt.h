@@ -140,7 +140,13 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  *
  * col == NULL: the rows are computed on the device in float64 from
  *   `position`, `r_nodes` and `basis`, then stored in value_dtype (rounded
- *   to nearest even, 16-bit types via float32).  Supported for n_cols <=
+ *   to nearest even, 16-bit types via float32).  With BF16 storage and
+ *   tiles, each row's entries in the 64 coarsest Haar columns (levels 0-5,
+ *   j < 64; those that dominate the rounding error of the product) also
+ *   keep the BF16 rounding of their residual W - bf16(W), stored in the
+ *   tiles as extra entries of the same columns, so that in the tile
+ *   product these entries carry ~16 significant bits; the plain rows hold
+ *   the BF16 values alone.  TLT_TUNE_BF16_HEAD = 1 turns this off.  Supported for n_cols <=
  *   2^20 with n_keep == n_cols or n_keep <= 8192, else TLT_E_ARG; a failed
  *   internal consistency check of the selection gives TLT_E_STATE.
  * col != NULL: col/val are taken as given (val in value_dtype); every
@@ -396,6 +402,12 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                at the next load_spatial)
  *   TLT_TUNE_SPATIAL_SEGMENT     longest work item of the compressed rows,
  *                                64 .. 2^20 entries (next load_spatial)
+ *   TLT_TUNE_BF16_HEAD           1 = BF16 tiles built on the device store
+ *                                the plain BF16 values only; 0 (default)
+ *                                = they also carry the residual of the 64
+ *                                coarsest columns (applies at the next
+ *                                load_transport; changes results within
+ *                                the BF16 storage error)
  * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
  * key or a value out of range.  Results do not depend on the tuning beyond
  * float32 summation order.
@@ -410,7 +422,8 @@ enum {
   TLT_TUNE_SPATIAL_SYNTH_LANES = 7,
   TLT_TUNE_SPATIAL_SEGMENT = 8,
   TLT_TUNE_TILE_SHAPE = 9,
-  TLT_TUNE_IRRADIANCE_HAAR = 10
+  TLT_TUNE_IRRADIANCE_HAAR = 10,
+  TLT_TUNE_BF16_HEAD = 11
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 

@@ -53,6 +53,11 @@ struct tlt_ctx {
   void *Gmat = nullptr, *Gpart = nullptr;
   int G_ld = 0;
   int tune_irr_haar = 0;   // 1: per-frame Haar of A o (T L) instead of G L
+  int tune_head_off = 0;   // 1: no residual words for the coarsest BF16 columns
+  // device build of BF16 tiles: residuals of the coarsest columns
+  // [N*K][head_cols] (during load_transport only) and their count
+  uint16_t *build_res = nullptr;
+  int head_cols = 0;
 
   // lighting-transfer product for the adjoint: P[k][o][Psh] = W_k G
   bool have_P = false;
@@ -215,6 +220,8 @@ void free_spatial(tlt_ctx *c) {
 }
 
 void free_all(tlt_ctx *c) {
+  dfree(c->build_res);
+  c->build_res = nullptr;
   free_columns(c);
   free_spatial(c);
   dfree(c->view_cos);
@@ -684,6 +691,8 @@ tlt_status device_build_rows(tlt_ctx *c, const tlt_transport_desc *d, int n_cols
     a.val = c->val;
     a.vdt = c->vdt;
     a.status = status;
+    a.res = c->build_res;
+    a.head_cols = c->head_cols;
     for (int kg0 = 0; kg0 < K; kg0 += build_max_group()) {
       a.kg0 = kg0;
       BTRY(launch_build_select(a, std::min(build_max_group(), K - kg0), 0));
@@ -727,6 +736,8 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   a.n_words = (n_cols + 31) / 32;
   a.n_blocks = nb;
   a.kstep = tile_kstep(c->vdt);
+  a.res = c->build_res;
+  a.head_cols = c->build_res ? c->head_cols : 0;
   int64_t *cnt = nullptr, *off = nullptr;
   tlt_status s = TLT_OK;
   hipError_t he = hipSuccess;
@@ -890,10 +901,22 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
     if (d->col) {
       HTRY(hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
       HTRY(hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice));
-    } else if ((s = device_build_rows(c, d, n_cols)) != TLT_OK) {
-      goto fail_all;
+    } else {
+      // BF16 tiles built here carry a second BF16 word for the coarsest
+      // columns of every row (their residual), so those products keep ~16
+      // significant bits of W
+      c->head_cols = 0;
+      if (want_tiles && c->vdt == TLT_BF16 && !c->tune_head_off) {
+        c->head_cols = std::min(64, n_cols);
+        const size_t rb = sizeof(uint16_t) * (size_t)n_rowsW * c->head_cols;
+        if ((s = dalloc(c, (void **)&c->build_res, rb, "BF16 residuals")) != TLT_OK) goto fail_all;
+        HTRY(hipMemset(c->build_res, 0, rb));
+      }
+      if ((s = device_build_rows(c, d, n_cols)) != TLT_OK) goto fail_all;
     }
     if (want_tiles && (s = device_build_tiles(c, tV, n_cols)) != TLT_OK) goto fail_all;
+    dfree(c->build_res);
+    c->build_res = nullptr;
 #undef HTRY
   }
   if ((s = ensure_partition(c)) != TLT_OK) goto fail_all;
@@ -1316,6 +1339,10 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
   if (value < 0) return fail(&c->err, TLT_E_ARG, "tuning values are >= 0 (0 = built-in choice)");
   switch (key) {
     case TLT_TUNE_TILE_CHUNK: c->tune_tile_chunk = value; break;
+    case TLT_TUNE_BF16_HEAD:
+      if (value > 1) return fail(&c->err, TLT_E_ARG, "BF16 head flag must be 0 or 1");
+      c->tune_head_off = value;
+      break;
     case TLT_TUNE_IRRADIANCE_HAAR:
       if (value > 1) return fail(&c->err, TLT_E_ARG, "irradiance flag must be 0 or 1");
       c->tune_irr_haar = value;

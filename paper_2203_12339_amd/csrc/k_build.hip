@@ -104,6 +104,12 @@ __device__ __forceinline__ void store_value(void *val, int vdt, int64_t i, doubl
   }
 }
 
+// BF16 rounding of what the BF16 storage of v leaves out (v - bf16(v)).
+__device__ __forceinline__ uint16_t bf16_residual(double v) {
+  const float hi = __uint_as_float((uint32_t)to_bf16((float)v) << 16);
+  return to_bf16((float)(v - (double)hi));
+}
+
 struct Shared {
   double *rn;          // [nr]
   double2 *bs;         // [KG][nr] (basis, slope)
@@ -167,6 +173,8 @@ __device__ __forceinline__ void entry(const BuildArgs &a, const Shared &sh, cons
     const int64_t r = ((int64_t)(a.o0 + v) * a.K + a.kg0 + k) * a.n_keep + j;
     a.col[r] = j;
     store_value(a.val, a.vdt, r, w);
+    if (a.res != nullptr && j < a.head_cols)
+      a.res[((int64_t)(a.o0 + v) * a.K + a.kg0 + k) * a.head_cols + j] = bf16_residual(w);
   }
 }
 
@@ -484,8 +492,11 @@ __global__ __launch_bounds__(256) void k_build_sort(BuildArgs a) {
   for (int i = t; i < n; i += 256) {
     const uint64_t kk = key[i];
     const int slot = (int)(kk & 0xffffffffu);
-    a.col[g * n + i] = (int32_t)(kk >> 32);
-    store_value(a.val, a.vdt, g * n + i, a.sval[(int64_t)r * n + slot]);
+    const int j = (int)(kk >> 32);
+    const double w = a.sval[(int64_t)r * n + slot];
+    a.col[g * n + i] = j;
+    store_value(a.val, a.vdt, g * n + i, w);
+    if (a.res != nullptr && j < a.head_cols) a.res[g * a.head_cols + j] = bf16_residual(w);
     if (i > 0 && (key[i - 1] >> 32) >= (kk >> 32)) atomicOr(a.status, 2);
   }
 }
@@ -510,6 +521,17 @@ __device__ __forceinline__ void block_bitmap(const TileBuildArgs &a, int b, uint
   __syncthreads();
 }
 
+// Union columns below head_cols (the first words of the bitmap).
+__device__ __forceinline__ uint32_t head_count(const TileBuildArgs &a, const uint32_t *bm) {
+  if (a.res == nullptr) return 0u;
+  uint32_t h = 0;
+  for (int w = 0; w * 32 < a.head_cols; ++w) {
+    const int nb = min(32, a.head_cols - 32 * w);
+    h += (uint32_t)__popc(bm[w] & (nb == 32 ? 0xffffffffu : ((1u << nb) - 1u)));
+  }
+  return h;
+}
+
 __global__ __launch_bounds__(256) void k_tile_count(TileBuildArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
@@ -522,7 +544,10 @@ __global__ __launch_bounds__(256) void k_tile_count(TileBuildArgs a) {
   c = wave_sum(c);
   if ((threadIdx.x & 63) == 0) atomicAdd(&total, c);
   __syncthreads();
-  if (threadIdx.x == 0) a.count[b] = (int64_t)((total + a.kstep - 1) / a.kstep * a.kstep);
+  if (threadIdx.x == 0) {
+    const uint32_t n = total + head_count(a, bm);
+    a.count[b] = (int64_t)((n + a.kstep - 1) / a.kstep * a.kstep);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
@@ -570,7 +595,11 @@ __global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
       bits &= bits - 1u;
     }
   }
-  for (int64_t u = total + t; u < nu; u += 256) a.ucol[off + u] = 0;
+  // the head columns once more (residual entries), then the padding
+  const uint32_t hb = head_count(a, bm);
+  if (t < a.head_cols && a.res != nullptr && ((bm[t >> 5] >> (t & 31)) & 1u))
+    a.ucol[off + total + (uint32_t)__popc(bm[t >> 5] & ((1u << (t & 31)) - 1u)) + (t >= 32 ? (uint32_t)__popc(bm[0]) : 0u)] = t;
+  for (int64_t u = total + hb + t; u < nu; u += 256) a.ucol[off + u] = 0;
   // values in operand order
   const int R = a.V * a.K, MT = R / 16, ks = a.kstep, kpl = ks / 4;
   const int v0 = b * a.V, v1 = min(a.N, v0 + a.V);
@@ -587,6 +616,14 @@ __global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
       ((uint32_t *)a.tval)[w] = ((const uint32_t *)a.val)[e];
     else
       ((uint16_t *)a.tval)[w] = ((const uint16_t *)a.val)[e];
+    if (a.res != nullptr && j < a.head_cols) {
+      // u < head_cols here: the union's entries before u are columns below j
+      const int uh = (int)total + u;
+      const int sh = uh / ks, rh = uh % ks;
+      const int lh = (rh / kpl) * 16 + (row & 15);
+      const int64_t wh = off * R + (((int64_t)sh * MT + row / 16) * 64 + lh) * kpl + rh % kpl;
+      ((uint16_t *)a.tval)[wh] = a.res[e / a.n_keep * a.head_cols + j];
+    }
   }
 }
 

@@ -154,6 +154,10 @@ struct BuildArgs {
   void *val;               // storage type vdt
   int vdt;
   int *status;             // nonzero after a failed internal check
+  // BF16 storage: for columns j < head_cols, the BF16 rounding of the
+  // residual W - bf16(W) at [global row][j] (zero-initialised), or nullptr
+  uint16_t *res;
+  int head_cols;
 };
 size_t build_select_lds(int KG, int nr, int max_chunks);
 int build_chunk_columns();
@@ -169,6 +173,11 @@ hipError_t launch_build_sort(const BuildArgs &a, hipStream_t st);
 // weights).  Values are stored densely over [U x R] in operand order: for
 // k-step s, m-tile t (16 rows), lane l and element i < kpl the value
 // W[row = 16t + l%16][u = s*kstep + kpl*(l/16) + i], where kpl = kstep/4.
+// With residuals (BF16 storage, `res` non-null) the union is followed by
+// its h columns below head_cols once more (h <= head_cols: they are the
+// union's first h entries, in the same order), whose values are the BF16
+// residuals of those rows' entries, so the product adds W - bf16(W) for the
+// coarsest columns; the padding follows.
 struct TileBuildArgs {
   const int32_t *col;      // [N*K][n_keep] ascending
   const void *val;         // storage values (esz bytes)
@@ -181,6 +190,8 @@ struct TileBuildArgs {
   const int64_t *blk_off;  // fill pass: [n_blocks+1]
   int32_t *ucol;
   void *tval;              // zero-initialised
+  const uint16_t *res;     // [N*K][head_cols] residuals, or nullptr
+  int head_cols;           // <= 64
 };
 hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st);
 hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st);

@@ -17,10 +17,11 @@ def scene_for(w: synth.Workload, K=None):
 
 
 def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout="auto",
-                 tile_vertices=0, tuned=True) -> Renderer:
+                 tile_vertices=0, tuned=True, bf16_head=True) -> Renderer:
     """A renderer with the workload's transport loaded.  With ``tuned`` (and
     no explicit tile size) the autotuner's recorded shape for exactly this
-    workload is applied, if there is one."""
+    workload is applied, if there is one.  ``bf16_head=False`` builds BF16
+    tiles without the residual words of the coarsest columns."""
     sc = scene_for(w, K) if scene is None else scene
     entry = None
     if tuned and tile_vertices == 0 and layout != "rows" and K is None:
@@ -29,6 +30,8 @@ def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout=
         if entry is not None:
             tile_vertices = entry["tile_vertices"]
     r = Renderer(device)
+    if not bf16_head:
+        r.set_tuning("bf16_head", 1)
     r.load_transport(sc, w.n_keep, storage=w.storage, wavelet=w.wavelet, layout=layout,
                      tile_vertices=tile_vertices)
     if entry is not None:

@@ -96,6 +96,11 @@ def test_full_size_sampled_rows(name, n_rows):
     e = normwise(got, ref)
     say(f"[full] {name}: normwise {e:.3e} elementwise {elementwise(got, ref):.3e}")
     assert e <= TOL[w.storage], e
+    if w.storage == "bf16":
+        # the residual words of the coarsest columns keep BF16 tiles well
+        # inside the tolerance (without them the worst output set of all
+        # 40962 rows reaches 5.3e-3; with them 1.7e-3)
+        assert e <= 2.5e-3, e
     if w.n_cfg == 1:
         rng = np.random.default_rng(11)
         bb_rows = rng.standard_normal((w.n_out, n_rows, 3))
@@ -509,3 +514,22 @@ def test_autotune_sweeps_shapes_that_all_match_oracle():
             _, _, _, B = _render(w, L, th, renderer=r)
             assert normwise(B, ref) <= TOL["f32"], (V, kc)
         r.close()
+
+
+def test_bf16_head_residual_lowers_error():
+    """BF16 tiles built on the device carry the residual of the coarsest
+    columns: same oracle, within tolerance either way, and a clearly smaller
+    error with the residual words than without them."""
+    w = _workload("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=16, n_cfg=16))
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ref = oracle_scene(w).render(L, th)
+    errs = {}
+    for head in (True, False):
+        r = renderer_for(w, bf16_head=head)
+        _, _, _, B = _render(w, L, th, renderer=r)
+        errs[head] = normwise(B, ref)
+        assert errs[head] <= TOL["bf16"], (head, errs[head])
+        r.close()
+    say(f"[bf16 head] normwise with residuals {errs[True]:.3e}, without {errs[False]:.3e}")
+    assert errs[True] <= 0.7 * errs[False], errs
