@@ -294,7 +294,8 @@ class Renderer:
 
     # -- transport --------------------------------------------------------
     def load_transport(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None,
-                       layout="auto", tile_vertices=0):
+                       layout="auto", tile_vertices=0, transfer=None):
+        """transfer: storage of T (default: the storage of W; F64 only with F64)."""
         N = scene["perm"].shape[0]
         n_pad = 1 << (N - 1).bit_length()
         vdt = DTYPES[storage]
@@ -315,7 +316,7 @@ class Renderer:
         d.n_r = arrs["r_nodes"].shape[0]
         d.wavelet = self.wavelet
         d.value_dtype = vdt
-        d.transfer_dtype = vdt
+        d.transfer_dtype = DTYPES[transfer] if transfer else vdt
         d.n_keep = self.n_keep
         d.layout = LAYOUTS[layout]
         d.tile_vertices = int(tile_vertices)

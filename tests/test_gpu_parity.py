@@ -533,3 +533,33 @@ def test_bf16_head_residual_lowers_error():
         r.close()
     say(f"[bf16 head] normwise with residuals {errs[True]:.3e}, without {errs[False]:.3e}")
     assert errs[True] <= 0.7 * errs[False], errs
+
+
+@pytest.mark.parametrize("name,kw", [("batch64-bf16-40962:n16", dict(subdiv=0, n_light=2, n_cfg=2, keep=0.5)),
+                                     ("batch64-bf16-40962:n64", dict(subdiv=1, n_light=3, n_cfg=3, keep=0.5)),
+                                     ("batch64-bf16-40962:n64-all", dict(subdiv=1, n_light=3, n_cfg=3, keep=1.0))],
+                         ids=["16-columns", "64-columns", "64-columns-untruncated"])
+def test_bf16_residuals_cover_small_meshes(name, kw):
+    """With at most 64 columns every kept entry carries its residual word:
+    with the transfer vectors in FP32, BF16 tiles then reproduce the oracle
+    to ~16 significant bits of W (misplaced residuals would leave BF16-size
+    errors), and without the residuals they do not."""
+    from paper_2203_12339_amd.workloads import scene_for
+    w = _workload(name, kw)
+    sc = scene_for(w)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    ref = oracle_scene(w).render(L, th)
+    errs = {}
+    for head in (True, False):
+        r = tlt.Renderer(0)
+        if not head:
+            r.set_tuning("bf16_head", 1)
+        r.load_transport(sc, w.n_keep, storage="bf16", wavelet=w.wavelet, transfer="f32")
+        _, _, _, B = _render(w, L, th, renderer=r)
+        errs[head] = normwise(B, ref)
+        r.close()
+    say(f"[bf16 head] {name}: N={w.n_vertices} with residuals {errs[True]:.3e}, without {errs[False]:.3e}")
+    assert errs[True] <= 1e-4, errs
+    assert errs[False] <= TOL["bf16"], errs
+    assert errs[False] >= 10 * errs[True], errs
