@@ -180,6 +180,190 @@ __global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Ps
   }
 }
 
+// Float32 form with Lg staged in LDS.  The workgroup copies Lg of its
+// column group for every term into LDS once (rows padded to FOLD_LDW
+// floats, so the four lane groups of a B-operand read hit disjoint banks);
+// each wave then streams the P rows of its RT 16-row tiles with 16-byte
+// loads, one term ahead of their matrix work.  The contraction over lm is taken in a permuted order that makes
+// those loads contiguous: for the g-th group of 16 coefficients, lane group
+// lk loads P[o][16 g + 4 lk .. 16 g + 4 lk + 3] and its component v enters
+// matrix step (g, v) as contraction index 16 g + 4 lk + v; the B operand
+// is read from the Lg row of the same index.  The MS % 4 steps left over
+// (Psh not a multiple of 16) take one value per lane as in k_folded.
+constexpr int FOLD_LDW = FOLD_CG + 4;
+constexpr int FOLD_WPB = 8;   // waves per workgroup (they share the staged Lg)
+
+template <int NTN, int MS, int RT>
+__global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__restrict__ P, int Psh, int K,
+                                                    const float *__restrict__ Lg, int Cs, int C,
+                                                    int N, const int32_t *__restrict__ perm,
+                                                    float *__restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  float *lg = reinterpret_cast<float *>(smem);  // [K * Psh][FOLD_LDW]
+  constexpr int G4 = MS / 4, R4 = MS % 4;
+  const int t = threadIdx.x;
+  const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+  const int cg0 = blockIdx.y * FOLD_CG;
+  f32x4 acc[RT][NTN];
+  const float *prow[RT];
+  bool rok[RT];
+  constexpr int G4n = G4 > 0 ? G4 : 1, R4n = R4 > 0 ? R4 : 1;
+  // the A operands of term k (issued one term ahead of their matrix work)
+  auto load = [&](int k, float4 (&x4)[RT][G4n], float (&x1)[RT][R4n]) {
+    const int64_t koff = (int64_t)k * N * Psh;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+#pragma unroll
+      for (int g = 0; g < G4; ++g) x4[r][g] = *reinterpret_cast<const float4 *>(prow[r] + koff + 16 * g + 4 * lk);
+#pragma unroll
+      for (int q = 0; q < R4; ++q) x1[r][q] = prow[r][koff + 16 * G4 + 4 * q + lk];
+    }
+  };
+  // the B operands of a whole term are read from LDS before its matrix work
+  auto compute = [&](int k, const float4 (&x4)[RT][G4n], const float (&x1)[RT][R4n]) {
+    const float *lk_rows = lg + (size_t)k * Psh * FOLD_LDW + li;
+    float bv[MS][NTN];
+#pragma unroll
+    for (int g = 0; g < G4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int nt = 0; nt < NTN; ++nt) bv[4 * g + v][nt] = lk_rows[(16 * g + 4 * lk + v) * FOLD_LDW + nt * 16];
+#pragma unroll
+    for (int q = 0; q < R4; ++q)
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt) bv[4 * G4 + q][nt] = lk_rows[(16 * G4 + 4 * q + lk) * FOLD_LDW + nt * 16];
+#pragma unroll
+    for (int g = 0; g < G4; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const float av = rok[r] ? x4[r][g][v] : 0.f;
+#pragma unroll
+          for (int nt = 0; nt < NTN; ++nt) acc[r][nt] = mfma16(av, bv[4 * g + v][nt], acc[r][nt]);
+        }
+#pragma unroll
+    for (int q = 0; q < R4; ++q)
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const float av = rok[r] ? x1[r][q] : 0.f;
+#pragma unroll
+        for (int nt = 0; nt < NTN; ++nt) acc[r][nt] = mfma16(av, bv[4 * G4 + q][nt], acc[r][nt]);
+      }
+  };
+  float4 a4[RT][G4n], b4[RT][G4n];
+  float a1[RT][R4n], b1[RT][R4n];
+  // the workgroup stays resident and takes row blocks of 4 RT tiles in
+  // turn; the first term of the next block is requested before the
+  // current block's stores (and the first block's before the staging)
+  const int n_rb = ((N + 15) / 16 + FOLD_WPB * RT - 1) / (FOLD_WPB * RT);
+  auto rows = [&](int rb) {
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int o = ((rb * FOLD_WPB + wave) * RT + r) * 16 + li;
+      rok[r] = o < N;
+      prow[r] = P + (int64_t)min(o, N - 1) * Psh;
+    }
+  };
+  rows(blockIdx.x);
+  load(0, a4, a1);
+  // stage Lg[(k, lm)][cg0 .. cg0 + 63] (zero past Cs; Cs is a multiple of
+  // 16): 16-byte items, eight loads in flight per thread
+  const int nq = K * Psh * (FOLD_CG / 4);
+  constexpr int NTHR = FOLD_WPB * 64;
+  for (int i0 = 0; i0 < nq; i0 += NTHR * 8) {
+    float4 tmp[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NTHR + t;
+      const int row = i >> 4, col = cg0 + 4 * (i & 15);
+      tmp[u] = (i < nq && col < Cs) ? *reinterpret_cast<const float4 *>(Lg + (size_t)row * Cs + col)
+                                    : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NTHR + t;
+      if (i < nq) *reinterpret_cast<float4 *>(lg + (i >> 4) * FOLD_LDW + 4 * (i & 15)) = tmp[u];
+    }
+  }
+  __syncthreads();  // Lg staged
+  for (int rb = blockIdx.x; rb < n_rb; rb += gridDim.x) {
+    const int tile0 = (rb * FOLD_WPB + wave) * RT;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt) acc[r][nt] = f32x4{0, 0, 0, 0};
+    // term t sits in buffer t mod 2 and is requested one term ahead
+    for (int k = 0; k < K; k += 2) {
+      if (k + 1 < K) load(k + 1, b4, b1);
+      compute(k, a4, a1);
+      if (k + 1 < K) {
+        if (k + 2 < K) load(k + 2, a4, a1);
+        compute(k + 1, b4, b1);
+      }
+    }
+    // the next block's first term (its loads overlap these stores)
+    if (rb + (int)gridDim.x < n_rb) {
+      rows(rb + gridDim.x);
+      load(0, a4, a1);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int o = (tile0 + r) * 16 + 4 * lk + v;
+          const int c = cg0 + nt * 16 + li;
+          if (o < N && c < C) {
+            const int q = c / 3, ch = c - 3 * q;
+            B[((int64_t)q * N + perm[o]) * 3 + ch] = acc[r][nt][v];
+          }
+        }
+  }
+}
+
+size_t folded_lds_bytes(int K, int Psh) { return sizeof(float) * (size_t)K * Psh * FOLD_LDW; }
+
+template <int NTN, int MS>
+static void folded_lds_rt(dim3 gx, int tiles, hipStream_t st, const float *P, int Psh, int K,
+                          const float *Lg, int Cs, int C, int N, const int32_t *perm, float *B) {
+  // Resident workgroups: as many as fit two per compute unit (LDS allowing),
+  // split over the column groups; each takes row blocks of FOLD_WPB RT
+  // tiles in turn.  RT = 2 unless one tile per wave fills the resident
+  // slots, round by round, more than 10% better.
+  const size_t lds = folded_lds_bytes(K, Psh);
+  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds)));
+  const int gy = (int)gx.y;
+  const int slots = std::max(1, 256 * per_cu / gy);
+  auto fill = [&](int rt) {
+    const int nrb = (tiles + FOLD_WPB * rt - 1) / (FOLD_WPB * rt);
+    return (double)nrb / ((double)((nrb + slots - 1) / slots) * slots);
+  };
+  const int rt = fill(1) > 1.1 * fill(2) ? 1 : 2;
+  const int gxx = std::min((tiles + FOLD_WPB * rt - 1) / (FOLD_WPB * rt), slots);
+  if (rt == 2)
+    TLT_LAUNCH((k_folded_lds<NTN, MS, 2>), dim3(gxx, gy), dim3(FOLD_WPB * 64), lds, st, P, Psh, K, Lg,
+               Cs, C, N, perm, B);
+  else
+    TLT_LAUNCH((k_folded_lds<NTN, MS, 1>), dim3(gxx, gy), dim3(FOLD_WPB * 64), lds, st, P, Psh, K, Lg,
+               Cs, C, N, perm, B);
+}
+
+template <int NTN>
+static hipError_t folded_lds_ms(dim3 gx, int tiles, hipStream_t st, const float *P, int Psh, int K,
+                                const float *Lg, int Cs, int C, int N, const int32_t *perm, float *B) {
+  switch (Psh / 4) {
+#define CASE(m) \
+  case m: folded_lds_rt<NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(7) CASE(8) CASE(9) CASE(12) CASE(16)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
 template <typename CT, int NTN, int MS>
 static void folded_rt(dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh, int K, const CT *Lg,
                       int Cs, int C, int N, const int32_t *perm, CT *B) {
@@ -241,8 +425,19 @@ hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gc
   } else {
     TLT_LAUNCH(k_fold_weights<float>, dim3((nw + 255) / 256), dim3(256), 0, st,
                (const float *)gcol, Cs, (const float *)sh, cols, K, Psh, n_sh, (float *)scratch);
-    e = folded_go<float>(cols.C, Cs, gx, tiles, st, (const float *)P, Psh, K, (const float *)scratch,
-                         N, perm, (float *)B);
+    if (folded_lds_bytes(K, Psh) <= 144 * 1024) {
+      const int ntn = (std::min(FOLD_CG, cols.C) + 15) / 16;
+      const float *Pf = (const float *)P, *Lf = (const float *)scratch;
+      switch (ntn) {
+        case 1: e = folded_lds_ms<1>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
+        case 2: e = folded_lds_ms<2>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
+        case 3: e = folded_lds_ms<3>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
+        default: e = folded_lds_ms<4>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
+      }
+    } else {
+      e = folded_go<float>(cols.C, Cs, gx, tiles, st, (const float *)P, Psh, K, (const float *)scratch,
+                           N, perm, (float *)B);
+    }
   }
   if (e != hipSuccess) return e;
   return hipGetLastError();
