@@ -269,6 +269,9 @@ def main():
                     help="use the (column, value) row kernel instead of the tiles")
     ap.add_argument("--folded", action="store_true",
                     help="relight through the folded lighting transport B = sum_k g_k P_k L")
+    ap.add_argument("--material-edit", action="store_true",
+                    help="time material edits: each step sets one of two material sets and "
+                         "renders from the saved per-term transport (Steps 3 and 4 only)")
     ap.add_argument("--spatial", type=float, default=0.0, metavar="ENERGY",
                     help="render through the spatially compressed transport (CDF 9/7 over the "
                          "output vertices) keeping this fraction of the coefficient energy")
@@ -331,6 +334,9 @@ def main():
     if args.folded and (args.backward or args.plain):
         print("--folded excludes --backward and --plain", file=sys.stderr)
         sys.exit(2)
+    if args.material_edit and (args.backward or args.folded or args.spatial):
+        print("--material-edit excludes --backward, --folded and --spatial", file=sys.stderr)
+        sys.exit(2)
     flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0) | \
         (tlt.PLAIN_ROWS if args.plain else 0) | (tlt.FOLDED_LIGHTING if args.folded else 0) | \
         (tlt.SPATIAL if args.spatial else 0)
@@ -349,6 +355,21 @@ def main():
         r.render_raw(B.data_ptr(), flags)
         if args.backward:
             r.render_backward(dB, dSH, dTh)
+
+    if args.material_edit:
+        # one full render saves v_k; every step then edits the material (a
+        # host-validated set_material, as an application would call it) and
+        # renders: the weights and the combine over the saved v_k
+        r.render_raw(B.data_ptr(), flags | tlt.SAVE_FOR_BACKWARD)
+        mats = [tt, torch.tensor(synth.make_materials(w, seed=4242), dtype=torch.float64, device=dev)]
+        edit = [0]
+
+        def step():
+            edit[0] ^= 1
+            r.set_material(mats[edit[0]])
+            r.render_raw(B.data_ptr(), tlt.PLAIN_ROWS if args.plain else 0)
+
+        args.dist_steps = 0   # set_material synchronises: no graph capture, no per-step passes
 
     for _ in range(args.warmup):
         step()
@@ -369,10 +390,15 @@ def main():
             r.profile_pause()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_tr, n_tr = r.profile_read("transport")
+    ms_tr, n_tr = r.profile_read("combine" if args.material_edit else "transport")
     stage_ms = {s: r.profile_read(s) for s in ("weights", "irradiance", "transport", "adjoint")
-                + (("inverse",) if args.spatial else ())}
+                + (("inverse",) if args.spatial else ()) + (("combine",) if args.material_edit else ())}
     r.profile(False)
+    if args.material_edit:
+        # back to the first material set, so the accuracy check below sees
+        # a material edit rendered through the saved v_k
+        r.set_material(mats[0])
+        r.render_raw(B.data_ptr(), tlt.PLAIN_ROWS if args.plain else 0)
     ms_per_step = 1e3 * elapsed / args.steps
     shaded = w.n_vertices * w.n_out
     value = shaded * args.steps / elapsed
@@ -394,6 +420,12 @@ def main():
         alg_bytes = sp["nnz"] * (4 + esz) + n_rows * C * esz + w.n_vertices * C * esz
         kernel, traffic = "k_sp_rows", None
         flops = 2.0 * sp["nnz"] * C
+    elif args.material_edit:
+        # saved v_k (K x N x Cs) read once, B written once
+        cs = (C + 15) // 16 * 16
+        alg_bytes = w.K * w.n_vertices * cs * esz + w.n_vertices * C * esz
+        kernel, traffic = "k_combine", None
+        flops = 2.0 * w.K * w.n_vertices * C
     elif args.folded:
         # P_k rows read once (Psh >= n_sh columns, as stored), B written once
         psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
@@ -465,6 +497,7 @@ def main():
             "n_vertices": w.n_vertices, "K": w.K, "n_keep": w.n_keep, "n_sh": w.n_sh,
             "storage": w.storage, "lightings": w.n_light, "materials": w.n_cfg,
             "columns": C, "backward": bool(args.backward), "tile": r.tile(),
+            "material_edit": bool(args.material_edit),
             "layout": ("spatial" if args.spatial else "folded lighting" if args.folded
                        else ("rows" if args.plain else "tiles")),
             "spatial": sp,

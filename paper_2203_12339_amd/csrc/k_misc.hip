@@ -21,6 +21,47 @@ __global__ __launch_bounds__(256) void k_combine(const CT *__restrict__ V, int C
   B[((int64_t)q * N + perm[o]) * 3 + ch] = s;
 }
 
+// Float32 form: one thread per vertex and four consecutive columns (Cs is a
+// multiple of 16), the KT <= 16 terms' 16-byte loads of v_k all issued
+// before the sums, so each thread keeps KT loads in flight.
+template <int KT>
+__global__ __launch_bounds__(256) void k_combine4(const float *__restrict__ V, int Cs,
+                                                  const float *__restrict__ gcol, int K, int N, int C,
+                                                  const int32_t *__restrict__ perm,
+                                                  float *__restrict__ B) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int nq = Cs / 4;
+  if (t >= (int64_t)N * nq) return;
+  const int o = (int)(t / nq), c0 = 4 * (int)(t - (int64_t)o * nq);
+  if (c0 >= C) return;
+  float4 v[KT], g[KT];
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const int kk = min(k, K - 1);
+    v[k] = *reinterpret_cast<const float4 *>(V + ((int64_t)kk * N + o) * Cs + c0);
+    g[k] = *reinterpret_cast<const float4 *>(gcol + (size_t)kk * Cs + c0);
+  }
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    if (k < K) {
+      s[0] = fmaf(g[k].x, v[k].x, s[0]);
+      s[1] = fmaf(g[k].y, v[k].y, s[1]);
+      s[2] = fmaf(g[k].z, v[k].z, s[2]);
+      s[3] = fmaf(g[k].w, v[k].w, s[3]);
+    }
+  }
+  const int64_t po = perm[o];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = c0 + j;
+    if (c < C) {
+      const int q = c / 3, ch = c - 3 * q;
+      B[((int64_t)q * N + po) * 3 + ch] = s[j];
+    }
+  }
+}
+
 // Outgoing Fresnel factor of Eq. (3)/(6): B[q][perm[o]][ch] *= (1/pi)
 // F_t(eta[mat(q)][ch], w_o(o)), from cos(w_o, n) per Morton position (0 or
 // less: seen from behind, factor 0).  Unpolarised dielectric transmittance,
@@ -68,7 +109,19 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
   if (fp64)
     TLT_LAUNCH(k_combine<double>, dim3(blocks), dim3(256), 0, st, (const double *)V, Cs,
                        (const double *)gcol, K, N, C, perm, (double *)B);
-  else
+  else if (Cs % 16 == 0 && K <= 16) {
+    const int64_t n4 = (int64_t)N * (Cs / 4);
+    const unsigned b4 = (unsigned)((n4 + 255) / 256);
+    if (K <= 4)
+      TLT_LAUNCH(k_combine4<4>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol, K,
+                 N, C, perm, (float *)B);
+    else if (K <= 8)
+      TLT_LAUNCH(k_combine4<8>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol, K,
+                 N, C, perm, (float *)B);
+    else
+      TLT_LAUNCH(k_combine4<16>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol,
+                 K, N, C, perm, (float *)B);
+  } else
     TLT_LAUNCH(k_combine<float>, dim3(blocks), dim3(256), 0, st, (const float *)V, Cs,
                        (const float *)gcol, K, N, C, perm, (float *)B);
   return hipGetLastError();

@@ -217,6 +217,25 @@ def test_linearity_and_material_only_update():
     r.close()
 
 
+def test_material_only_update_batched():
+    """Material edits of a batched 16-bit launch (48 columns, K = 8): the
+    combine over the saved v_k equals a full render and the oracle."""
+    w = _workload("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=16, n_cfg=16))
+    say("[material edit] batch64 shrunk, 16 configurations")
+    r, L, _, _ = _render(w, save=True)
+    for seed in (999, 1000):
+        th2 = synth.make_materials(w, seed=seed)
+        r.set_material(dev_tensor(th2, "f64"))
+        Bm = r.render().cpu().numpy()
+        r.set_material(dev_tensor(th2, "f64"))
+        Bf = r.render(force=True, save=True).cpu().numpy()
+        assert normwise(Bm, Bf) <= 2e-6, normwise(Bm, Bf)
+        e = normwise(Bm, oracle_scene(w).render(L, th2))
+        say(f"[material edit] seed {seed}: vs full render {normwise(Bm, Bf):.2e}, vs oracle {e:.3e}")
+        assert e <= TOL["bf16"], e
+    r.close()
+
+
 @pytest.mark.parametrize("name,kw", [("dense-f64-642", {}),
                                      ("haar-f32-10242:small-ragged", dict(subdiv=1, n_light=3, n_cfg=1)),
                                      ("haar-f32-10242", {}),
