@@ -291,6 +291,12 @@ def main():
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py is single-process; WORLD_SIZE > 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    for mode, excl in (("spatial", ("folded", "backward", "plain")), ("folded", ("backward", "plain")),
+                       ("material_edit", ("backward", "folded", "spatial"))):
+        if getattr(args, mode) and any(getattr(args, e) for e in excl):
+            print(f"--{mode.replace('_', '-')} excludes " + ", ".join(f"--{e}" for e in excl),
+                  file=sys.stderr)
+            sys.exit(2)
 
     import numpy as np
     import torch
@@ -310,9 +316,6 @@ def main():
     log(f"[bench] precompute + load {time.perf_counter() - t0:.1f}s")
     sp = None
     if args.spatial:
-        if args.folded or args.backward or args.plain:
-            print("--spatial excludes --folded, --backward and --plain", file=sys.stderr)
-            sys.exit(2)
         t0 = time.perf_counter()
         r.load_spatial(args.spatial)
         nnz, levels, _, e_k = r.spatial_info()
@@ -331,12 +334,7 @@ def main():
     r.set_material(tt)
     B = torch.empty((w.n_out, w.n_vertices, 3), dtype=ldt, device=dev)
     dB = torch.randn_like(B) if args.backward else None
-    if args.folded and (args.backward or args.plain):
-        print("--folded excludes --backward and --plain", file=sys.stderr)
-        sys.exit(2)
-    if args.material_edit and (args.backward or args.folded or args.spatial):
-        print("--material-edit excludes --backward, --folded and --spatial", file=sys.stderr)
-        sys.exit(2)
+
     flags = tlt.FORCE_FULL | (tlt.SAVE_FOR_BACKWARD if args.backward else 0) | \
         (tlt.PLAIN_ROWS if args.plain else 0) | (tlt.FOLDED_LIGHTING if args.folded else 0) | \
         (tlt.SPATIAL if args.spatial else 0)
