@@ -97,6 +97,21 @@ def test_host_error_paths():
     assert "row out of range" in tlt._last_error(None).decode()
 
 
+def test_read_probe_rejects_bad_arguments_before_any_device_call():
+    """The read probe validates its arguments on the host: these calls
+    return TLT_E_ARG without launching anything (no GPU needed)."""
+    import ctypes
+    P = ctypes.c_void_p
+    dummy = P(16)   # never dereferenced: every call below is rejected first
+    for buf, nbytes, out, blocks in ((None, 32, dummy, 4),     # no buffer
+                                     (dummy, 24, dummy, 4),    # not a multiple of 16
+                                     (dummy, -16, dummy, 4),   # negative size
+                                     (dummy, 32, None, 4),     # no output
+                                     (dummy, 32, dummy, 0)):   # no workgroups
+        assert tlt.STATUS[tlt._read_probe(buf, nbytes, out, blocks, None)] == "TLT_E_ARG"
+    assert "bad arguments" in tlt._last_error(None).decode()
+
+
 def test_autotune_candidates_and_table():
     """Every candidate tile shape is one the tile kernel accepts, and the
     recorded table (if any) only names such shapes."""
