@@ -237,20 +237,22 @@ __global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Ps
 // column group for every term into LDS once (rows padded to FOLD_LDW
 // floats, so the four lane groups of a B-operand read hit disjoint banks);
 // each wave then streams the P rows of its RT 16-row tiles with 16-byte
-// loads, one term ahead of their matrix work.  The contraction over lm is taken in a permuted order that makes
-// those loads contiguous: for the g-th group of 16 coefficients, lane group
-// lk loads P[o][16 g + 4 lk .. 16 g + 4 lk + 3] and its component v enters
-// matrix step (g, v) as contraction index 16 g + 4 lk + v; the B operand
-// is read from the Lg row of the same index.  The MS % 4 steps left over
-// (Psh not a multiple of 16) take one value per lane as in k_folded.
+// loads, one term ahead of their matrix work.  The contraction over lm is
+// taken in a permuted order that makes those loads contiguous: for the
+// g-th group of 16 coefficients, lane group lk loads
+// P[o][16 g + 4 lk .. 16 g + 4 lk + 3] and its component v enters matrix
+// step (g, v) as contraction index 16 g + 4 lk + v; the B operand is read
+// from the Lg row of the same index.  The MS % 4 steps left over (Psh not a
+// multiple of 16) take one value per lane as in k_folded.
 constexpr int FOLD_LDW = FOLD_CG + 4;
 constexpr int FOLD_WPB = 8;   // waves per workgroup (they share the staged Lg)
 
 template <int NTN, int MS, int RT>
-__global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__restrict__ P, int Psh, int K,
-                                                    const float *__restrict__ Lg, int Cs, int C,
-                                                    int N, const int32_t *__restrict__ perm,
-                                                    float *__restrict__ B) {
+__global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__restrict__ P, int Psh,
+                                                              int K, const float *__restrict__ Lg,
+                                                              int Cs, int C, int N,
+                                                              const int32_t *__restrict__ perm,
+                                                              float *__restrict__ B) {
   extern __shared__ __align__(16) unsigned char smem[];
   float *lg = reinterpret_cast<float *>(smem);  // [K * Psh][FOLD_LDW]
   constexpr int G4 = MS / 4, R4 = MS % 4;
