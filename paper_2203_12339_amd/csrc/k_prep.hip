@@ -184,6 +184,57 @@ __device__ __forceinline__ void store_e(CT *ehat, uint32_t *ehat2, int split, si
   }
 }
 
+// Haar levels of one chunk with R = ch_rows / 16 rows per thread: thread
+// (g = threadIdx.x / 16, column cc = threadIdx.x % 16) takes rows g R ..
+// g R + R - 1 of its column into registers and runs the log2 R levels whose
+// pairs lie inside them without any barrier; the 16 sums per column left
+// then go through LDS once, and one thread per column runs the last four
+// levels.  Every detail and sum is the same expression of the same two
+// values as in the level-by-level form, so the results are identical.
+template <int R, typename CT>
+__device__ void haar_chunk(const PrepArgs &a, CT *x, int chunk, int c0, CT *ehat, uint32_t *ehat2,
+                           CT *partial) {
+  const CT h = CT(0.70710678118654752440);
+  const int cc = threadIdx.x & 15, g = threadIdx.x >> 4;
+  CT v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = x[(g * R + r) * TL_STRIDE + cc];
+  int half = a.ch_rows >> 1;
+#pragma unroll
+  for (int n = R; n > 1; n >>= 1) {
+#pragma unroll
+    for (int p = 0; p < n / 2; ++p) {
+      const CT lo = v[2 * p], hi = v[2 * p + 1];
+      const int64_t j = (int64_t)half * (a.n_chunks + chunk) + g * (n / 2) + p;
+      store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (lo - hi) * h);
+      v[p] = (lo + hi) * h;
+    }
+    half >>= 1;
+  }
+  __syncthreads();  // every thread has read its rows of x
+  x[g * TL_STRIDE + cc] = v[0];
+  __syncthreads();
+  if (g != 0) return;
+  CT u[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) u[r] = x[r * TL_STRIDE + cc];
+#pragma unroll
+  for (int n = 16; n > 1; n >>= 1) {
+#pragma unroll
+    for (int p = 0; p < n / 2; ++p) {
+      const CT lo = u[2 * p], hi = u[2 * p + 1];
+      const int64_t j = (int64_t)half * (a.n_chunks + chunk) + p;
+      store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (lo - hi) * h);
+      u[p] = (lo + hi) * h;
+    }
+    half >>= 1;
+  }
+  if (a.n_chunks == 1)
+    store_e(ehat, ehat2, a.split, (size_t)c0 + cc, u[0]);
+  else
+    partial[(size_t)chunk * a.Cs + c0 + cc] = u[0];
+}
+
 template <typename TT, typename CT>
 __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
   typedef typename MfmaOut<CT>::V4 V4;
@@ -305,6 +356,14 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
     return;
   }
 
+  switch (a.ch_rows) {
+    case 16: haar_chunk<1, CT>(a, x, chunk, c0, ehat, ehat2, partial); return;
+    case 32: haar_chunk<2, CT>(a, x, chunk, c0, ehat, ehat2, partial); return;
+    case 64: haar_chunk<4, CT>(a, x, chunk, c0, ehat, ehat2, partial); return;
+    case 128: haar_chunk<8, CT>(a, x, chunk, c0, ehat, ehat2, partial); return;
+    case 256: haar_chunk<16, CT>(a, x, chunk, c0, ehat, ehat2, partial); return;
+    default: break;
+  }
   const CT h = CT(0.70710678118654752440);
   for (int len = a.ch_rows; len > 1; len >>= 1) {
     const int half = len >> 1;
