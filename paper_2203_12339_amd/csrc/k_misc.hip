@@ -845,24 +845,27 @@ __global__ __launch_bounds__(256) void k_adj_reduce2(const double *__restrict__ 
 template <typename CT>
 __global__ void k_adj_out(const double *__restrict__ red, const double *__restrict__ dg64, int K,
                           int n_sh, Cols cols, CT *__restrict__ dSH, double *__restrict__ dTheta) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
   const int C = cols.C;
   const double *gbar = red;             // [K][C]
   const double *X = red + (size_t)K * C; // [C][n_sh]
   const int n_th = cols.n_mat * 9;
   const int n_l = cols.n_light * n_sh * 3;
-  if (t < n_th) {
+  if (gt < n_th * 64) {
+    // one wave per material derivative: lanes take (output set, term)
+    // pairs with independent loads, then a fixed-order wave sum
+    const int t = gt >> 6, lane = gt & 63;
     const int m = t / 9, ch = (t / 3) % 3, p = t % 3;
     double s = 0.0;
-    for (int q = 0; q < cols.n_out; ++q) {
+    for (int i = lane; i < cols.n_out * K; i += 64) {
+      const int q = i / K, k = i - q * K;
       const int mq = cols.n_mat > 1 ? q : 0;
-      if (mq != m) continue;
-      const int c = 3 * q + ch;
-      for (int k = 0; k < K; ++k) s += gbar[(size_t)k * C + c] * dg64[(((size_t)m * 3 + ch) * K + k) * 3 + p];
+      if (mq == m) s += gbar[(size_t)k * C + 3 * q + ch] * dg64[(((size_t)m * 3 + ch) * K + k) * 3 + p];
     }
-    dTheta[t] = s;
-  } else if (t < n_th + n_l) {
-    const int u = t - n_th;
+    s = wave_sum(s);
+    if (lane == 0) dTheta[t] = s;
+  } else if (gt < n_th * 64 + n_l) {
+    const int u = gt - n_th * 64;
     const int l = u / (n_sh * 3), lm = (u / 3) % n_sh, ch = u % 3;
     double s = 0.0;
     for (int q = 0; q < cols.n_out; ++q) {
@@ -886,7 +889,7 @@ hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, 
   if (partial_bytes < l.total) return hipErrorInvalidValue;
   double *stage1 = (double *)((char *)partial + l.stage1);
   double *red = (double *)((char *)partial + l.red);
-  const int n_fin = cols.n_mat * 9 + cols.n_light * n_sh * 3;
+  const int n_fin = cols.n_mat * 9 * 64 + cols.n_light * n_sh * 3;  // a wave per material derivative
   const dim3 gr((nout + 63) / 64, ADJ_SPLIT);
   if (fp64) {
     const dim3 g1(nblk, (nout + 255) / 256);
