@@ -9,8 +9,13 @@ original vertex order -- every stage recomputed (TLT_FORCE_FULL).  With
 before timing starts.  Prints one JSON line on stdout; progress goes to
 stderr.
 
-  python bench.py [--config haar-f32-10242|batch64-bf16-40962|large-f16-163842]
-                  [--steps K] [--warmup W] [--gpus 1]
+  python bench.py [--config large-f16-163842|batch64-bf16-40962|haar-f32-10242]
+                  [--steps K] [--warmup W] [--gpus 1] [--[no-]backward]
+
+The default workload is the large one (163842 vertices, 1% of the Haar
+coefficients kept in FP16, 16 lightings) with forward and adjoint in every
+step, its error taken against the FP64 oracle on its 2048 seeded output
+vertices.
 """
 from __future__ import annotations
 
@@ -62,8 +67,9 @@ def stored_traffic(workload, C):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, L, th, budget_s=12.0):
-    """The FP64 oracle (O-B) on a bounded sample of output rows, 1 thread."""
+def cpu_baseline(w, L, th, budget_s=12.0, pool=None):
+    """The FP64 oracle (O-B) on a bounded sample of output rows, 1 thread
+    (drawn from ``pool`` when given, else from all vertices)."""
     import numpy as np
     try:
         from threadpoolctl import threadpool_limits
@@ -74,13 +80,14 @@ def cpu_baseline(w, L, th, budget_s=12.0):
     sc = Scene(w)
     rng = np.random.default_rng(12345)
     limit = threadpool_limits(limits=1) if threadpool_limits else contextlib.nullcontext()
+    cand = np.arange(w.n_vertices) if pool is None else np.asarray(pool)
     with limit:
-        probe = rng.choice(w.n_vertices, size=min(16, w.n_vertices), replace=False)
+        probe = rng.choice(cand, size=min(16, len(cand)), replace=False)
         t0 = time.perf_counter()
         sc.render_vertices(L, th, probe, block=16)
         per_row = (time.perf_counter() - t0) / len(probe)
-        n = int(min(w.n_vertices, max(16, budget_s / max(per_row, 1e-6))))
-        rows = np.sort(rng.choice(w.n_vertices, size=n, replace=False))
+        n = int(min(len(cand), max(16, budget_s / max(per_row, 1e-6))))
+        rows = np.sort(rng.choice(cand, size=n, replace=False))
         t0 = time.perf_counter()
         ref = sc.render_vertices(L, th, rows, block=32)
         dt = time.perf_counter() - t0
@@ -200,13 +207,27 @@ _SCENE = None
 
 
 def _oracle_chunk(args):
-    L, th, rows = args
-    return _SCENE.render_vertices(L, th, rows, block=32)
+    """Forward radiance of a chunk of output vertices and, with an upstream
+    gradient on them, that chunk's share of the adjoint (the restricted-rows
+    adjoint is linear and additive over disjoint row sets)."""
+    import numpy as np
+
+    from oracle import adjoint
+    L, th, rows, bb = args
+    ref = _SCENE.render_vertices(L, th, rows, block=32)
+    if bb is None:
+        return ref, None, None
+    inv = np.empty(_SCENE.N, dtype=np.int64)
+    inv[_SCENE.perm] = np.arange(_SCENE.N)
+    gL, gT = adjoint.grad(_SCENE, L, th, bb, rows=inv[rows], block=32)
+    return ref, gL, gT
 
 
-def oracle_all_cores_child(name, rows_path):
+def oracle_all_cores_child(name, rows_path, bb_path, out_path):
     """Child process of the CPU baseline (no GPU in it): the same oracle on
-    the same sample, split over a fork pool of the host cores."""
+    the same sample, split over a fork pool of the host cores; with an
+    upstream gradient also the FP64 adjoint on those rows.  Writes the
+    results to out_path (.npz) and prints the timing."""
     global _SCENE
     import multiprocessing as mp
 
@@ -218,20 +239,28 @@ def oracle_all_cores_child(name, rows_path):
     L, th = synth.make_lighting(w), synth.make_materials(w)
     _SCENE = Scene(w)
     rows = np.load(rows_path)
+    bb = np.load(bb_path) if bb_path != "-" else None        # [n_out, len(rows), 3]
     n = max(1, min(16, os.cpu_count() or 1))
-    chunks = [c for c in np.array_split(rows, 4 * n) if len(c)]
+    splits = [c for c in np.array_split(np.arange(len(rows)), 4 * n) if len(c)]
+    jobs = [(L, th, rows[c], None if bb is None else bb[:, c, :]) for c in splits]
     with mp.get_context("fork").Pool(n) as pool:
-        pool.map(_oracle_chunk, [(L, th, chunks[0][:1])] * n)        # workers up
+        pool.map(_oracle_chunk, [(L, th, rows[:1], None)] * n)        # workers up
         t0 = time.perf_counter()
-        pool.map(_oracle_chunk, [(L, th, c) for c in chunks])
+        res = pool.map(_oracle_chunk, jobs)
         dt = time.perf_counter() - t0
+    ref = np.concatenate([r[0] for r in res], axis=1)
+    out = {"ref": ref}
+    if bb is not None:
+        out["gL"] = sum(r[1] for r in res)
+        out["gT"] = sum(r[2] for r in res)
+    np.savez(out_path, **out)
     print(json.dumps({"value": round(len(rows) * w.n_out / dt, 3), "cores": n,
-                      "seconds": round(dt, 2)}), flush=True)
+                      "seconds": round(dt, 2), "adjoint": bb is not None}), flush=True)
 
 
-def cpu_all_cores(w, rows):
+def cpu_all_cores(w, rows, bb=None):
     """Runs oracle_all_cores_child in a fresh interpreter (this process holds
-    the GPU; the child never touches it) -> dict or None."""
+    the GPU; the child never touches it) -> (timing dict, results) or None."""
     import subprocess
     import tempfile
 
@@ -239,30 +268,40 @@ def cpu_all_cores(w, rows):
     with tempfile.TemporaryDirectory(dir="/tmp") as d:
         path = os.path.join(d, "rows.npy")
         np.save(path, np.asarray(rows))
+        bpath = "-"
+        if bb is not None:
+            bpath = os.path.join(d, "bb.npy")
+            np.save(bpath, np.asarray(bb))
+        opath = os.path.join(d, "out.npz")
         env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
         try:
             out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-all-cores",
-                                  w.name, path], capture_output=True, text=True, timeout=300, env=env)
+                                  w.name, path, bpath, opath], capture_output=True, text=True,
+                                 timeout=600, env=env)
         except subprocess.TimeoutExpired:
+            log("[bench] all-cores oracle timed out")
             return None
         if out.returncode != 0:
             log(f"[bench] all-cores oracle failed: {out.stderr[-300:]}")
             return None
-        return json.loads(out.stdout.strip().splitlines()[-1])
+        with np.load(opath) as z:
+            res = {k: z[k] for k in z.files}
+        return json.loads(out.stdout.strip().splitlines()[-1]), res
 
 
 def main():
-    if len(sys.argv) == 4 and sys.argv[1] == "--oracle-all-cores":
-        oracle_all_cores_child(sys.argv[2], sys.argv[3])
+    if len(sys.argv) == 6 and sys.argv[1] == "--oracle-all-cores":
+        oracle_all_cores_child(*sys.argv[2:6])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="haar-f32-10242",
-                    choices=["haar-f32-10242", "batch64-bf16-40962", "large-f16-163842"])
-    ap.add_argument("--backward", action="store_true",
-                    help="include the adjoint in every step")
+    ap.add_argument("--config", default="large-f16-163842",
+                    choices=["large-f16-163842", "batch64-bf16-40962", "haar-f32-10242"])
+    ap.add_argument("--backward", action=argparse.BooleanOptionalAction, default=None,
+                    help="include the adjoint in every step (default: for the workload that "
+                         "states forward + adjoint, large-f16-163842)")
     ap.add_argument("--tile", type=int, default=0, help="columns per lane (0 = tuned default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", action="store_true",
@@ -282,6 +321,9 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.backward is None:
+        args.backward = args.config == "large-f16-163842" and not (
+            args.folded or args.spatial or args.material_edit)
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the transport "
@@ -355,19 +397,20 @@ def main():
             r.render_backward(dB, dSH, dTh)
 
     if args.material_edit:
-        # one full render saves v_k; every step then edits the material (a
-        # host-validated set_material, as an application would call it) and
-        # renders: the weights and the combine over the saved v_k
+        # one full render saves v_k; every step then edits the material --
+        # new values written into the material buffer on the device, then
+        # set_material (no host round trip: the values are validated by the
+        # weights kernel) -- and renders: the weights and the combine over the
+        # saved v_k (Steps 3 and 4 only).  The step is graph-capturable.
         r.render_raw(B.data_ptr(), flags | tlt.SAVE_FOR_BACKWARD)
-        mats = [tt, torch.tensor(synth.make_materials(w, seed=4242), dtype=torch.float64, device=dev)]
+        mats = [tt.clone(), torch.tensor(synth.make_materials(w, seed=4242), dtype=torch.float64, device=dev)]
         edit = [0]
 
         def step():
             edit[0] ^= 1
-            r.set_material(mats[edit[0]])
+            tt.copy_(mats[edit[0]])
+            r.set_material(tt)
             r.render_raw(B.data_ptr(), tlt.PLAIN_ROWS if args.plain else 0)
-
-        args.dist_steps = 0   # set_material synchronises: no graph capture, no per-step passes
 
     for _ in range(args.warmup):
         step()
@@ -395,8 +438,10 @@ def main():
     if args.material_edit:
         # back to the first material set, so the accuracy check below sees
         # a material edit rendered through the saved v_k
-        r.set_material(mats[0])
+        tt.copy_(mats[0])
+        r.set_material(tt)
         r.render_raw(B.data_ptr(), tlt.PLAIN_ROWS if args.plain else 0)
+    assert r.material_status() == tlt.OK
     ms_per_step = 1e3 * elapsed / args.steps
     shaded = w.n_vertices * w.n_out
     value = shaded * args.steps / elapsed
@@ -431,51 +476,109 @@ def main():
         kernel, traffic = "k_folded", None
         flops = 2.0 * w.K * w.n_vertices * w.n_sh * C
     else:
+        # kept (index, value) entries read once, Ehat read once, B written
+        # once, and with the adjoint the per-term v_k written once
         alg_bytes = nnz * (4 + vsz) + n_rows * C * esz + w.n_vertices * C * esz
+        if args.backward:
+            alg_bytes += w.K * w.n_vertices * C * esz
         kernel = "k_stream" if args.plain else "k_tiles"
-        traffic = None if args.plain else stored_traffic(w.name, C)
+        traffic = None if args.plain or args.backward else stored_traffic(w.name, C)
         flops = 2.0 * nnz * C
     avg_s = ms_tr / max(n_tr, 1) * 1e-3
-    achieved = alg_bytes / avg_s / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+    warm = {"kernel_us": round(avg_s * 1e6, 2), "achieved": round(alg_bytes / avg_s / 1e9, 1),
+            "frac": round(alg_bytes / avg_s / 1e9 / HBM_PEAK_GBS, 4)}
+    cold = None
+    if timing and "transport_us" in timing.get("cold", {}):
+        cold_s = timing["cold"]["transport_us"] * 1e-6
+        cold = {"kernel_us": timing["cold"]["transport_us"], "achieved": round(alg_bytes / cold_s / 1e9, 1),
+                "frac": round(alg_bytes / cold_s / 1e9 / HBM_PEAK_GBS, 4)}
+    # A transport whose bytes fit the 256 MB Infinity Cache is reported from
+    # the cold steps (the cache evicted before each); larger ones stream from
+    # HBM either way and are reported from the timed region.
+    fits_cache = alg_bytes <= 1.05 * (256 << 20)
+    prim = cold if (fits_cache and cold is not None) else warm
+    roofline = {"bound": "hbm", "achieved": prim["achieved"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": prim["frac"],
                 "traffic": traffic, "kernel": kernel,
-                "kernel_us": round(avg_s * 1e6, 2), "kernel_launches_timed": n_tr,
-                "algorithmic_bytes": alg_bytes}
+                "kernel_us": prim["kernel_us"], "kernel_launches_timed": n_tr,
+                "algorithmic_bytes": alg_bytes,
+                "basis": ("cold steps (Infinity Cache evicted before each)" if prim is cold
+                          else "timed region (every 8th step)"),
+                "warm": warm}
     if copy_gbs:
         roofline["reference_GBps"] = {"copy": round(copy_gbs[0], 1), "read": round(copy_gbs[1], 1),
                                       "buffer_load_read": round(copy_gbs[2], 1),
                                       "source": "torch copy_ and sum, and the library's read "
                                                 "probe, over 1 GiB on this GPU"}
-    if timing and "transport_us" in timing.get("cold", {}):
-        cold_s = timing["cold"]["transport_us"] * 1e-6
-        roofline["cold"] = {"kernel_us": timing["cold"]["transport_us"],
-                            "achieved": round(alg_bytes / cold_s / 1e9, 1),
-                            "frac": round(alg_bytes / cold_s / 1e9 / HBM_PEAK_GBS, 4)}
+    if cold is not None:
+        roofline["cold"] = cold
+    roofline_adj = None
+    if args.backward and stage_ms["adjoint"][1] > 0:
+        # saved v_k and the lighting-transfer product P read once, the
+        # upstream gradient read once (outputs are a few KB)
+        psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
+        adj_bytes = (w.K * w.n_vertices * C + w.K * w.n_vertices * psh + w.n_vertices * C) * esz
+        adj_s = stage_ms["adjoint"][0] / stage_ms["adjoint"][1] * 1e-3
+        roofline_adj = {"bound": "hbm", "achieved": round(adj_bytes / adj_s / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(adj_bytes / adj_s / 1e9 / HBM_PEAK_GBS, 4),
+                        "stage_us": round(adj_s * 1e6, 2), "algorithmic_bytes": adj_bytes,
+                        "kernels": "adjoint stage (all its launches)"}
     ai = flops / alg_bytes
 
     # accuracy of this very output on a sample of rows + the CPU oracle time
     Bh = B.cpu().numpy()
     cpu = None
     rel_err = None
+    grad_err = None
+    err_rows = None
     if args.spatial and not args.no_cpu_baseline:
         log("[bench] no CPU baseline for the spatial path: its oracle needs every output "
             "coefficient (dense per-term CDF 9/7 transforms), not a sample of rows")
     if not args.no_cpu_baseline and not args.spatial:
-        log("[bench] timing the FP64 oracle on a sample of rows ...")
-        rows, ref, dt = cpu_baseline(w, L, th)
-        got = Bh[:, rows, :].astype(np.float64)
-        rel_err = float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
-        cpu = {"value": round(len(rows) * w.n_out / dt, 3), "unit": "vertices/s", "cores": 1,
+        def rel(got, ref):
+            got = np.asarray(got, dtype=np.float64)
+            return float((np.abs(got - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+
+        # the workload's own seeded output vertices (2048 for the large one),
+        # else the single-thread sample drawn below
+        stated = synth.sample_rows(w) if w.sample_rows else None
+        log("[bench] timing the FP64 oracle on a sample of rows, 1 thread ...")
+        rows1, ref1, dt = cpu_baseline(w, L, th, pool=stated)
+        cpu = {"value": round(len(rows1) * w.n_out / dt, 3), "unit": "vertices/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{len(rows)} seeded output vertices x {w.n_out} configs of {w.name}, "
+               "sample": f"{len(rows1)} seeded output vertices x {w.n_out} configs of {w.name}, "
                          f"O-B float64 (row precompute + transport), 1 thread, {dt:.1f}s"}
-        log(f"[bench] oracle {cpu['value']} vertices/s; GPU rel err on sample {rel_err:.3e}")
-        allc = cpu_all_cores(w, rows)
+        log(f"[bench] oracle {cpu['value']} vertices/s on 1 thread")
+        err_rows = stated if stated is not None else rows1
+        bb = None
+        if args.backward:
+            # one more forward + adjoint with the upstream gradient on the
+            # error rows only: the oracle's restricted-rows adjoint is then
+            # the full one
+            bb = np.random.default_rng(11).standard_normal((w.n_out, len(err_rows), 3))
+            dBm = torch.zeros_like(B)
+            dBm[:, torch.as_tensor(err_rows, device=dev), :] = torch.as_tensor(bb, dtype=B.dtype, device=dev)
+            r.render_raw(B.data_ptr(), flags)
+            r.render_backward(dBm, dSH, dTh)
+            torch.cuda.synchronize()
+            Bh = B.cpu().numpy()
+            gL_gpu, gT_gpu = dSH.cpu().numpy(), dTh.cpu().numpy()
+        allc = cpu_all_cores(w, err_rows, bb)
         if allc is not None:
-            cpu["all_cores"] = {"value": allc["value"], "unit": "vertices/s", "cores": allc["cores"],
-                                "sample": "the same vertices, a fork pool of one-thread workers"}
-            log(f"[bench] oracle on {allc['cores']} cores: {allc['value']} vertices/s")
+            t_all, res = allc
+            cpu["all_cores"] = {"value": t_all["value"], "unit": "vertices/s", "cores": t_all["cores"],
+                                "sample": f"{len(err_rows)} seeded output vertices, a fork pool of "
+                                          f"one-thread workers" + (", forward + adjoint" if bb is not None else "")}
+            log(f"[bench] oracle on {t_all['cores']} cores: {t_all['value']} vertices/s")
+            rel_err = rel(Bh[:, err_rows, :], res["ref"])
+            if bb is not None:
+                grad_err = {"lighting": float(np.abs(gL_gpu - res["gL"]).max() / np.abs(res["gL"]).max()),
+                            "material": float(np.abs(gT_gpu - res["gT"]).max() / np.abs(res["gT"]).max())}
+        else:
+            err_rows = rows1
+            rel_err = rel(Bh[:, rows1, :], ref1)
+        log(f"[bench] GPU rel err on {len(err_rows)} rows {rel_err:.3e}"
+            + (f"; gradients {grad_err}" if grad_err else ""))
 
     out = {
         "metric": "shaded vertices/sec (K-term wavelet transport) at stated rel. err; % HBM peak",
@@ -502,10 +605,16 @@ def main():
             "tile_shape": ({"tile_vertices": r.tuning["tile_vertices"], "tile_chunk": r.tuning["tile_chunk"],
                             "wave_shape": r.tuning.get("tile_shape", 0) or "built-in",
                             "source": "autotuner table"} if getattr(r, "tuning", None) else "built-in"),
-            "rel_err_vs_fp64_oracle": rel_err, "arith_intensity_flop_per_byte": round(ai, 3),
+            "rel_err_vs_fp64_oracle": rel_err,
+            "rel_err_rows": None if err_rows is None else int(len(err_rows)),
+            "grad_rel_err_vs_fp64_oracle": grad_err,
+            "precision": ("f64 storage and arithmetic" if w.storage == "f64" else
+                          f"{w.storage} storage of W and T, f32 accumulation, f64 material weights"),
+            "arith_intensity_flop_per_byte": round(ai, 3),
             "stage_us": {k: round(v[0] / max(v[1], 1) * 1e3, 2) for k, v in stage_ms.items()},
         },
         "roofline": roofline,
+        "roofline_adjoint": roofline_adj,
         "cpu_baseline": cpu,
         "timing": timing,
     }

@@ -44,6 +44,7 @@ typedef struct tlt_ctx tlt_ctx;
 typedef enum {
   TLT_OK = 0,
   TLT_W_MATERIAL_OUT_OF_RANGE = 1, /* warning: material outside the PCA table */
+  TLT_W_BF16_NO_RESIDUAL = 2,      /* warning: BF16 products without the residual words */
   TLT_E_ARG = -1,                  /* bad argument, shape or value */
   TLT_E_STATE = -2,                /* call out of order */
   TLT_E_OOM = -3,                  /* device or host allocation failed */
@@ -149,9 +150,20 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  *   the BF16 values alone.  TLT_TUNE_BF16_HEAD = 1 turns this off.  Supported for n_cols <=
  *   2^20 with n_keep == n_cols or n_keep <= 8192, else TLT_E_ARG; a failed
  *   internal consistency check of the selection gives TLT_E_STATE.
- * col != NULL: col/val are taken as given (val in value_dtype); every
- *   column is checked to lie in [0, n_cols) and rows to ascend, else
- *   TLT_E_FORMAT.
+ * col != NULL: col/val are taken as given; every column is checked to lie
+ *   in [0, n_cols) and rows to ascend, else TLT_E_FORMAT.  val holds
+ *   value_dtype values (val_is_f64 = 0), or float64 values (val_is_f64 =
+ *   1) that the library rounds to value_dtype on the device as the device
+ *   build does -- with BF16 tiles they then also keep the residual words of
+ *   the coarsest columns (the rows tlt_build_rows writes, loaded this way,
+ *   give the same transport as col == NULL).
+ * Warning TLT_W_BF16_NO_RESIDUAL (the transport is loaded and usable): BF16
+ *   storage whose tiles carry no residual words (rows given as BF16 values,
+ *   layout ROWS, tiles impossible, or TLT_TUNE_BF16_HEAD = 1).  Plain BF16
+ *   values keep 8 significant bits of every coefficient; at 2% kept on
+ *   40962 vertices the worst output set then reaches ~5e-3 relative error
+ *   against the float64 operator, at the edge of the 5e-3 bound, against
+ *   ~2e-3 with the residual words.
  * n_cols = n_pad (HAAR, n_pad = next power of two >= N) or N (NONE).
  *
  * Layout.  The rows are always kept as (column, value) pairs (the plain
@@ -187,26 +199,58 @@ typedef struct {
   const double *mat_range;   /* [3][2] (lo, hi) of the PCA table, or NULL */
   int32_t layout;            /* TLT_LAYOUT_*: AUTO = tiles for non-F64 storage */
   int32_t tile_vertices;     /* vertices per tile block (0 = automatic) */
+  int32_t val_is_f64;        /* col != NULL: 1 = val holds float64 values, 0 = value_dtype */
 } tlt_transport_desc;
+
+/*
+ * Host-only validation of a transport description (no GPU work, no
+ * context): every check load_transport makes before it touches the device
+ * -- sizes, dtypes, layout, the permutation (TLT_E_FORMAT unless a
+ * bijection of 0..N-1), areas (> 0, finite), and for given rows each column
+ * in [0, n_cols) and strictly ascending per row (else TLT_E_FORMAT).
+ * Returns TLT_OK or the status load_transport would return for these
+ * reasons; the message is in tlt_last_error(NULL).
+ */
+tlt_status tlt_check_transport(const tlt_transport_desc *desc);
 
 tlt_status tlt_create(tlt_ctx **out, int hip_device);
 void tlt_destroy(tlt_ctx *ctx);
 const char *tlt_last_error(const tlt_ctx *ctx);
 
-/* Loads (or builds) the transport and uploads the geometry. Synchronous. */
+/*
+ * Loads (or builds) the transport and uploads the geometry (precompute of
+ * Sec. 3.1 and 3.2, Step 1).  Synchronous.  All host checks (those of
+ * tlt_check_transport) run before any device work, so a refused
+ * description leaves the context as it was.  May return the warning
+ * TLT_W_BF16_NO_RESIDUAL (loaded).
+ */
 tlt_status load_transport(tlt_ctx *ctx, const tlt_transport_desc *desc);
 
 /*
- * Material for the next render: theta_dev [n_mat][3 channels][sigma_a,
- * sigma_s', eta] float64 in device memory, owned by the caller and read on
- * `hip_stream` by render (it must stay valid until that render completes).
- * Copies the values to the host once (synchronising the stream) to
- * validate them: sigma_a > 0, sigma_s' > 0, eta >= 1, all finite, else
- * TLT_E_ARG.  Values outside mat_range give TLT_W_MATERIAL_OUT_OF_RANGE but
- * are accepted.  Marks the material weights dirty (Step 3 of Sec. 4).
+ * Material for the next render (Step 3 of Sec. 4: a material edit reruns
+ * the weights g_k of Sec. 2.2 / Eq. 4 and the combine of Step 4):
+ * theta_dev [n_mat][3 channels][sigma_a, sigma_s', eta] float64 in device
+ * memory, owned by the caller and read on render's stream (it must stay
+ * valid until that render completes; values written to it before a later
+ * render, or a graph replay, are the ones used).  Records the pointer and
+ * marks the weights dirty; no copy, no synchronisation (hip_stream is
+ * unused).  The values are validated by the weights kernel on the device:
+ * a channel with sigma_a <= 0, sigma_s' <= 0, eta < 1 or a non-finite value
+ * gets NaN weights (its radiance is NaN) and raises an invalid flag; a
+ * valid channel outside mat_range raises a range flag and renders
+ * normally.  tlt_material_status reports the flags.  TLT_E_ARG for
+ * n_mat < 1 or NULL, TLT_E_STATE before load_transport.
  */
 tlt_status set_material(tlt_ctx *ctx, int n_mat, const double *theta_dev,
                         void *hip_stream);
+
+/*
+ * Waits for hip_stream and reports, then clears, the material flags of the
+ * renders since the last call: TLT_E_ARG if a rendered material channel was
+ * invalid (the message names one), else TLT_W_MATERIAL_OUT_OF_RANGE if one
+ * lay outside the PCA table's range (mat_range), else TLT_OK.
+ */
+tlt_status tlt_material_status(tlt_ctx *ctx, void *hip_stream);
 
 /*
  * Lighting for the next render: sh_dev [n_light][n_sh][3] in device memory
@@ -259,6 +303,9 @@ tlt_status set_view(tlt_ctx *ctx, const double *eye, const double *position, con
  * TLT_E_STATE without load_spatial, TLT_E_ARG combined with
  * TLT_SAVE_FOR_BACKWARD, TLT_PLAIN_ROWS or TLT_FOLDED_LIGHTING.
  * TLT_E_STATE before load_transport / set_material / set_lighting.
+ * Warning TLT_W_BF16_NO_RESIDUAL (rendered): the product of a BF16
+ * transport ran without residual words -- TLT_PLAIN_ROWS (the row kernel
+ * holds the BF16 values alone) or tiles loaded without them.
  */
 tlt_status render(tlt_ctx *ctx, void *B_dev, void *hip_stream, int flags);
 

@@ -15,10 +15,16 @@ class TranslucentRender(torch.autograd.Function):
         renderer.set_material(theta.detach().contiguous())
         B = renderer.render(save=True)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
         return B
 
     @staticmethod
     def backward(ctx, dB):
+        # the library keeps the state of its latest render only: a render or
+        # load after this forward would give the gradients of other inputs
+        if ctx.renderer.generation != ctx.generation:
+            raise RuntimeError("the renderer rendered again after this forward; backward would use "
+                               "the state of the later render")
         dSH, dTheta = ctx.renderer.render_backward(dB.contiguous())
         return None, dSH, dTheta
 

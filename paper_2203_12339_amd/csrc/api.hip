@@ -34,6 +34,7 @@ struct tlt_ctx {
 
   // transport
   bool loaded = false;
+  bool bf16_plain = false;   // BF16 storage without residual words in the tiles
   int N = 0, n_pad = 0, n_sh = 0, n_shp = 0, K = 0, nr = 0, wavelet = 0, vdt = 0, tdt = 0;
   int64_t n_keep = 0;
   int n_rows = 0;  // rows of Ehat: n_pad (Haar) or N (plain)
@@ -76,6 +77,9 @@ struct tlt_ctx {
   int n_light = 0;
   const double *theta = nullptr;
   int n_mat = 0;
+  // material validation flags written by the weights kernel (see PrepArgs):
+  // pinned, coherent host memory, read by tlt_material_status
+  int *mstat = nullptr, *mstat_dev = nullptr;
   bool mat_dirty = true, light_dirty = true;
 
   // column-dependent buffers
@@ -123,8 +127,10 @@ struct tlt_ctx {
   int tune_tile_chunk = 0, tune_waves_per_cu = 0, tune_stream_epl = 0, tune_stream_nt = 0;
   int tune_tile_shape = 0;
 
-  // transport partition: n_waves equal row ranges; split vertices cleared
+  // transport partition: n_waves equal row ranges of part_rows = N*K rows;
+  // split vertices cleared
   int n_waves = 0;
+  int64_t part_rows = 0;
   int32_t *zero_v = nullptr;
   int n_zero = 0;
 
@@ -239,6 +245,8 @@ void free_all(tlt_ctx *c) {
   dfree(c->P);
   dfree(c->zero_v);
   c->n_zero = 0;
+  c->n_waves = 0;   // the partition belongs to the freed transport
+  c->part_rows = 0;
   dfree(c->t_off);
   dfree(c->t_ucol);
   dfree(c->t_val);
@@ -305,6 +313,12 @@ PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
   a.nr = c->nr;
   a.K = c->K;
   a.gk_stage = (size_t)c->K * c->nr <= 4096;   // 32 KB of basis in LDS
+  a.mstat = c->mstat_dev;
+  a.has_range = c->has_range;
+  for (int p = 0; p < 3; ++p) {
+    a.mat_lo[p] = c->mat_range[2 * p];
+    a.mat_hi[p] = c->mat_range[2 * p + 1];
+  }
   a.T = c->T;
   a.N = c->N;
   a.n_sh = c->n_sh;
@@ -322,24 +336,29 @@ PrepArgs prep_args(tlt_ctx *c, int Cs, Cols cols) {
 tlt_status ensure_partition(tlt_ctx *c) {
   const int wpc = c->tune_waves_per_cu > 0 ? c->tune_waves_per_cu : 32;
   const int nw = stream_waves(c->N, c->K, wpc);
-  if (nw == c->n_waves && (c->zero_v || c->n_zero == 0)) return TLT_OK;
+  const int64_t R = (int64_t)c->N * c->K;
+  if (nw == c->n_waves && R == c->part_rows) return TLT_OK;
   dfree(c->zero_v);
   c->n_zero = 0;
-  c->n_waves = nw;
-  const int64_t R = (int64_t)c->N * c->K, q = R / nw, rem = R % nw;
+  c->n_waves = 0;
+  c->part_rows = 0;
+  const int64_t q = R / nw, rem = R % nw;
   std::vector<int32_t> z;
   for (int64_t w = 1; w < nw; ++w) {
     const int64_t r0 = w * q + std::min<int64_t>(w, rem);
     if (r0 % c->K) z.push_back((int32_t)(r0 / c->K));  // Morton position
   }
-  if (z.empty()) return TLT_OK;
-  std::vector<int32_t> hp(c->N);
-  HIPC(c, hipMemcpy(hp.data(), c->perm, sizeof(int32_t) * c->N, hipMemcpyDeviceToHost));
-  for (auto &v : z) v = hp[v];                           // original vertex id
-  tlt_status s = dalloc(c, (void **)&c->zero_v, sizeof(int32_t) * z.size(), "split vertices");
-  if (s != TLT_OK) return s;
-  HIPC(c, hipMemcpy(c->zero_v, z.data(), sizeof(int32_t) * z.size(), hipMemcpyHostToDevice));
-  c->n_zero = (int)z.size();
+  if (!z.empty()) {
+    std::vector<int32_t> hp(c->N);
+    HIPC(c, hipMemcpy(hp.data(), c->perm, sizeof(int32_t) * c->N, hipMemcpyDeviceToHost));
+    for (auto &v : z) v = hp[v];                         // original vertex id
+    tlt_status s = dalloc(c, (void **)&c->zero_v, sizeof(int32_t) * z.size(), "split vertices");
+    if (s != TLT_OK) return s;
+    HIPC(c, hipMemcpy(c->zero_v, z.data(), sizeof(int32_t) * z.size(), hipMemcpyHostToDevice));
+    c->n_zero = (int)z.size();
+  }
+  c->n_waves = nw;
+  c->part_rows = R;
   return TLT_OK;
 }
 
@@ -596,6 +615,14 @@ tlt_status tlt_create(tlt_ctx **out, int hip_device) {
   tlt_ctx *c = new (std::nothrow) tlt_ctx;
   if (!c) return fail(nullptr, TLT_E_OOM, "context allocation");
   c->device = hip_device;
+  e = hipHostMalloc((void **)&c->mstat, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->mstat_dev, c->mstat, 0);
+  if (e != hipSuccess) {
+    if (c->mstat) (void)hipHostFree(c->mstat);
+    delete c;
+    return fail(nullptr, TLT_E_HIP, std::string("material status word: ") + hipGetErrorString(e));
+  }
+  for (int i = 0; i < 4; ++i) c->mstat[i] = 0;
   *out = c;
   return TLT_OK;
 }
@@ -608,6 +635,7 @@ void tlt_destroy(tlt_ctx *c) {
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   c->pool.clear();
   free_all(c);
+  if (c->mstat) (void)hipHostFree(c->mstat);
   delete c;
 }
 
@@ -631,14 +659,7 @@ int tlt_get_tile(const tlt_ctx *c) { return c ? c->cpl : 0; }
 tlt_status device_build_rows(tlt_ctx *c, const tlt_transport_desc *d, int n_cols) {
   const int N = c->N, K = c->K, nr = c->nr;
   const int64_t n_keep = d->n_keep;
-  const bool all = n_keep == n_cols;
-  if (!all && n_keep > build_sort_max())
-    return fail(&c->err, TLT_E_ARG,
-                "device build keeps at most " + std::to_string(build_sort_max()) +
-                    " coefficients per row (or all); pass rows built on the host");
-  if (n_cols > (1 << 20)) return fail(&c->err, TLT_E_ARG, "device build supports at most 2^20 columns");
-  if (c->wavelet == TLT_WAVELET_HAAR && n_cols < 8)
-    return fail(&c->err, TLT_E_ARG, "device build of Haar rows needs n_pad >= 8");
+  const bool all = n_keep == n_cols;   // (limits checked with the description)
   const int chw = std::min(n_cols, build_chunk_columns());
   const int max_chunks = (n_cols + chw - 1) / chw;
   std::vector<double> slope((size_t)K * nr, 0.0);
@@ -755,7 +776,8 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   c->tV = tV;
   c->tR = tV * c->K;
   c->t_blocks = nb;
-  c->t_val_bytes = (size_t)ho[nb] * c->tR * a.esz;
+  // (the zeroed slack after the last block is read by its W ring)
+  c->t_val_bytes = (size_t)ho[nb] * c->tR * a.esz + TILE_VAL_SLACK;
   if ((s = dalloc(c, (void **)&c->t_off, sizeof(int64_t) * (nb + 1), "tile offsets")) != TLT_OK) goto out;
   if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * (size_t)ho[nb], "tile columns")) != TLT_OK) goto out;
   if ((s = dalloc(c, &c->t_val, c->t_val_bytes, "tile values")) != TLT_OK) goto out;
@@ -774,57 +796,116 @@ out:
   return s;
 }
 
-tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
-  if (!c || !d) return fail(c ? &c->err : nullptr, TLT_E_ARG, "NULL argument");
-  HIPC(c, hipSetDevice(c->device));
+}  // extern "C"
+
+namespace {
+
+// Layout of the tiles a descriptor asks for: vertices per block (0 when
+// tiles are not possible) and whether they are built.
+struct TilePlan {
+  int tV = 0;
+  bool ok = false, want = false;
+};
+
+TilePlan tile_plan(const tlt_transport_desc *d, int n_cols) {
+  TilePlan t;
+  t.tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K, d->value_dtype);
+  // (the tile build keeps two bitmaps of n_cols bits in LDS)
+  t.ok = t.tV > 0 && t.tV * d->K >= 48 && t.tV * d->K <= 128 && (t.tV * d->K) % 16 == 0 &&
+         (size_t)8 * ((n_cols + 31) / 32) <= (size_t)150 * 1024;
+  t.want = d->value_dtype != TLT_F64 && d->layout != TLT_LAYOUT_ROWS && t.ok;
+  return t;
+}
+
+// Every host-side check of a transport description, before any device
+// work: sizes, dtypes, the permutation, the areas and (when given) the
+// rows' columns.  TLT_E_ARG / TLT_E_FORMAT with a message in *err.
+tlt_status check_transport_desc(const tlt_transport_desc *d, std::string *err) {
+  if (!d) return fail(err, TLT_E_ARG, "NULL transport description");
   const int N = d->n_vertices;
-  if (N < 1) return fail(&c->err, TLT_E_ARG, "n_vertices must be >= 1");
+  if (N < 1) return fail(err, TLT_E_ARG, "n_vertices must be >= 1");
   if (d->wavelet != TLT_WAVELET_NONE && d->wavelet != TLT_WAVELET_HAAR)
-    return fail(&c->err, TLT_E_ARG, "unknown wavelet");
+    return fail(err, TLT_E_ARG, "unknown wavelet");
   int n_pad = 1;
   while (n_pad < N) n_pad <<= 1;
   if (d->wavelet == TLT_WAVELET_HAAR && d->n_pad != n_pad)
-    return fail(&c->err, TLT_E_ARG, "n_pad must be the next power of two >= n_vertices");
+    return fail(err, TLT_E_ARG, "n_pad must be the next power of two >= n_vertices");
   if (d->wavelet == TLT_WAVELET_HAAR && n_pad > (1 << 19))
-    return fail(&c->err, TLT_E_ARG, "n_pad above 2^19 is not supported");
+    return fail(err, TLT_E_ARG, "n_pad above 2^19 is not supported");
   const int n_cols = d->wavelet == TLT_WAVELET_HAAR ? n_pad : N;
-  if (d->n_sh < 1 || d->n_sh > 64) return fail(&c->err, TLT_E_ARG, "n_sh must be in 1..64");
-  if (d->K < 1 || d->K > 64) return fail(&c->err, TLT_E_ARG, "K must be in 1..64");
-  if (d->n_r < 2 || d->n_r > 1024) return fail(&c->err, TLT_E_ARG, "n_r must be in 2..1024");
-  if (d->n_keep < 1 || d->n_keep > n_cols) return fail(&c->err, TLT_E_ARG, "n_keep out of range");
+  if (d->n_sh < 1 || d->n_sh > 64) return fail(err, TLT_E_ARG, "n_sh must be in 1..64");
+  if (d->K < 1 || d->K > 64) return fail(err, TLT_E_ARG, "K must be in 1..64");
+  if (d->n_r < 2 || d->n_r > 1024) return fail(err, TLT_E_ARG, "n_r must be in 2..1024");
+  if (d->n_keep < 1 || d->n_keep > n_cols) return fail(err, TLT_E_ARG, "n_keep out of range");
   for (int dt : {d->value_dtype, d->transfer_dtype})
-    if (dt < TLT_F64 || dt > TLT_F16) return fail(&c->err, TLT_E_ARG, "unknown dtype");
+    if (dt < TLT_F64 || dt > TLT_F16) return fail(err, TLT_E_ARG, "unknown dtype");
   if ((d->value_dtype == TLT_F64) != (d->transfer_dtype == TLT_F64))
-    return fail(&c->err, TLT_E_ARG, "transfer is F64 exactly when the transport is F64");
+    return fail(err, TLT_E_ARG, "transfer is F64 exactly when the transport is F64");
+  if (d->layout < TLT_LAYOUT_AUTO || d->layout > TLT_LAYOUT_TILES) return fail(err, TLT_E_ARG, "unknown layout");
+  if (d->tile_vertices < 0) return fail(err, TLT_E_ARG, "tile_vertices must be >= 0");
+  if (d->val_is_f64 != 0 && d->val_is_f64 != 1) return fail(err, TLT_E_ARG, "val_is_f64 must be 0 or 1");
+  if (d->val_is_f64 && !d->col) return fail(err, TLT_E_ARG, "val_is_f64 applies to rows given in col/val");
   if (!d->transfer || !d->area || !d->perm || !d->r_nodes || !d->basis)
-    return fail(&c->err, TLT_E_ARG, "NULL geometry array");
-  if (!d->col && !d->position) return fail(&c->err, TLT_E_ARG, "need col/val or position");
-  if (d->col && !d->val) return fail(&c->err, TLT_E_ARG, "col given without val");
+    return fail(err, TLT_E_ARG, "NULL geometry array");
+  if (!d->col && !d->position) return fail(err, TLT_E_ARG, "need col/val or position");
+  if (d->col && !d->val) return fail(err, TLT_E_ARG, "col given without val");
+  const TilePlan tp = tile_plan(d, n_cols);
+  if (d->layout == TLT_LAYOUT_TILES && (d->value_dtype == TLT_F64 || !tp.ok))
+    return fail(err, TLT_E_ARG,
+                "tiles need non-F64 storage, 48 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
+  if (!d->col) {
+    // limits of the device build of the rows
+    if (d->n_keep != n_cols && d->n_keep > build_sort_max())
+      return fail(err, TLT_E_ARG,
+                  "device build keeps at most " + std::to_string(build_sort_max()) +
+                      " coefficients per row (or all); pass rows built on the host");
+    if (n_cols > (1 << 20)) return fail(err, TLT_E_ARG, "device build supports at most 2^20 columns");
+    if (d->wavelet == TLT_WAVELET_HAAR && n_cols < 8)
+      return fail(err, TLT_E_ARG, "device build of Haar rows needs n_pad >= 8");
+  }
   {
     std::vector<char> seen(N, 0);
     for (int i = 0; i < N; ++i) {
       const int p = d->perm[i];
-      if (p < 0 || p >= N || seen[p]) return fail(&c->err, TLT_E_FORMAT, "perm is not a permutation");
+      if (p < 0 || p >= N || seen[p]) return fail(err, TLT_E_FORMAT, "perm is not a permutation");
       seen[p] = 1;
     }
   }
   for (int i = 0; i < N; ++i)
     if (!(d->area[i] > 0.0) || !std::isfinite(d->area[i]))
-      return fail(&c->err, TLT_E_ARG, "areas must be positive and finite");
-
-  // validate a given transport before touching the device
-  const int64_t n_rowsW = (int64_t)N * d->K;
+      return fail(err, TLT_E_ARG, "areas must be positive and finite");
   if (d->col) {
+    const int64_t n_rowsW = (int64_t)N * d->K;
     for (int64_t r = 0; r < n_rowsW; ++r) {
       const int32_t *cr = d->col + r * d->n_keep;
       for (int64_t e = 0; e < d->n_keep; ++e) {
         if (cr[e] < 0 || cr[e] >= n_cols)
-          return fail(&c->err, TLT_E_FORMAT, "column index out of range in row " + std::to_string(r));
+          return fail(err, TLT_E_FORMAT, "column index out of range in row " + std::to_string(r));
         if (e > 0 && cr[e] <= cr[e - 1])
-          return fail(&c->err, TLT_E_FORMAT, "columns not ascending in row " + std::to_string(r));
+          return fail(err, TLT_E_FORMAT, "columns not ascending in row " + std::to_string(r));
       }
     }
   }
+  return TLT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tlt_status tlt_check_transport(const tlt_transport_desc *d) { return check_transport_desc(d, nullptr); }
+
+tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
+  if (!c || !d) return fail(c ? &c->err : nullptr, TLT_E_ARG, "NULL argument");
+  // every host check runs before the device is touched
+  tlt_status s = check_transport_desc(d, &c->err);
+  if (s != TLT_OK) return s;
+  HIPC(c, hipSetDevice(c->device));
+  const int N = d->n_vertices;
+  int n_pad = 1;
+  while (n_pad < N) n_pad <<= 1;
+  const int n_cols = d->wavelet == TLT_WAVELET_HAAR ? n_pad : N;
+  const int64_t n_rowsW = (int64_t)N * d->K;
 
   HIPC(c, hipDeviceSynchronize());
   free_all(c);
@@ -844,19 +925,16 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   c->has_range = d->mat_range != nullptr;
   if (c->has_range) std::memcpy(c->mat_range, d->mat_range, sizeof(c->mat_range));
 
-  tlt_status s;
   const size_t vsz = dtype_size(c->vdt);
   const size_t nnz = (size_t)n_rowsW * (size_t)d->n_keep;
-  const int tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K, d->value_dtype);
-  // (the tile build keeps two bitmaps of n_cols bits in LDS)
-  const bool tiles_ok = tV > 0 && tV * d->K >= 48 && tV * d->K <= 128 && (tV * d->K) % 16 == 0 &&
-                        (size_t)8 * ((n_cols + 31) / 32) <= (size_t)150 * 1024;
-  const bool want_tiles = !c->fp64 && d->layout != TLT_LAYOUT_ROWS && tiles_ok;
-  if (d->layout == TLT_LAYOUT_TILES && (c->fp64 || !tiles_ok)) {
-    s = fail(&c->err, TLT_E_ARG,
-             "tiles need non-F64 storage, 48 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
-    goto fail_all;
-  }
+  const TilePlan tp = tile_plan(d, n_cols);
+  const int tV = tp.tV;
+  const bool want_tiles = tp.want;
+  // BF16 tiles carry a second BF16 word for the coarsest columns of every
+  // row (their residual), so those products keep ~16 significant bits of
+  // W; it needs the float64 values (rows built here, or given as float64)
+  const bool head = want_tiles && c->vdt == TLT_BF16 && !c->tune_head_off && (!d->col || d->val_is_f64);
+  c->head_cols = head ? std::min(64, n_cols) : 0;
   if ((s = dalloc(c, (void **)&c->col, sizeof(int32_t) * nnz, "transport columns")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->val, vsz * nnz, "transport values")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, &c->T, dtype_size(c->tdt) * (size_t)N * c->n_sh + 64, "transfer")) != TLT_OK) goto fail_all;
@@ -864,6 +942,11 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   if ((s = dalloc(c, (void **)&c->perm, sizeof(int32_t) * N, "perm")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, (void **)&c->rn, sizeof(double) * c->nr, "r nodes")) != TLT_OK) goto fail_all;
   if ((s = dalloc(c, (void **)&c->basis, sizeof(double) * c->nr * c->K, "basis")) != TLT_OK) goto fail_all;
+  if (head) {
+    const size_t rb = sizeof(uint16_t) * (size_t)n_rowsW * c->head_cols;
+    if ((s = dalloc(c, (void **)&c->build_res, rb, "BF16 residuals")) != TLT_OK) goto fail_all;
+    HIPC(c, hipMemset(c->build_res, 0, rb));
+  }
   {
     hipError_t he = hipSuccess;
 #define HTRY(x) if ((he = (x)) != hipSuccess) { s = hip_fail(c, he, #x); goto fail_all; }
@@ -877,42 +960,39 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
       for (int i = 0; i < N; ++i) a[i] = (float)d->area[i];
       HTRY(hipMemcpy(c->area, a.data(), sizeof(float) * N, hipMemcpyHostToDevice));
     }
-    // staging buffer for float64 -> storage conversion
+    if (d->col) HTRY(hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
+    // float64 host values are rounded to storage on the device, in chunks
+    // through a staging buffer (rows given as float64 also write their
+    // residual words: the columns are already on the device)
     const size_t stage_elems = (size_t)1 << 24;
     double *stage = nullptr;
     if ((s = dalloc(c, (void **)&stage, sizeof(double) * stage_elems, "staging")) != TLT_OK) goto fail_all;
-    auto upload_q = [&](const double *src, void *dst, int dt, size_t n) -> hipError_t {
+    auto upload_q = [&](const double *src, void *dst, int dt, size_t n, bool rows) -> hipError_t {
       for (size_t o = 0; o < n; o += stage_elems) {
         const size_t m = std::min(stage_elems, n - o);
         hipError_t e2 = hipMemcpy(stage, src + o, sizeof(double) * m, hipMemcpyHostToDevice);
         if (e2 != hipSuccess) return e2;
-        e2 = launch_quantize(stage, (char *)dst + o * dtype_size(dt), dt, (int64_t)m, 0);
+        e2 = rows ? launch_quantize_rows(stage, c->col, dst, dt, (int64_t)o, (int64_t)m, d->n_keep,
+                                         c->build_res, c->head_cols, 0)
+                  : launch_quantize(stage, (char *)dst + o * dtype_size(dt), dt, (int64_t)m, 0);
         if (e2 != hipSuccess) return e2;
         e2 = hipStreamSynchronize(0);
         if (e2 != hipSuccess) return e2;
       }
       return hipSuccess;
     };
-    he = upload_q(d->transfer, c->T, c->tdt, (size_t)N * c->n_sh);
-    if (he != hipSuccess) { dfree(stage); s = hip_fail(c, he, "uploading transfer"); goto fail_all; }
+    he = upload_q(d->transfer, c->T, c->tdt, (size_t)N * c->n_sh, false);
+    if (he == hipSuccess && d->col && d->val_is_f64)
+      he = upload_q((const double *)d->val, c->val, c->vdt, nnz, true);
     dfree(stage);
-    // Rows given by the caller are uploaded as they are; otherwise they are
-    // built on the device.  Tiles are then built on the device from the rows.
+    if (he != hipSuccess) { s = hip_fail(c, he, "uploading transfer / transport values"); goto fail_all; }
+    // Rows given in storage precision are uploaded as they are; without
+    // rows they are built on the device.  Tiles are then built on the
+    // device from the rows.
     if (d->col) {
-      HTRY(hipMemcpy(c->col, d->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice));
-      HTRY(hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice));
-    } else {
-      // BF16 tiles built here carry a second BF16 word for the coarsest
-      // columns of every row (their residual), so those products keep ~16
-      // significant bits of W
-      c->head_cols = 0;
-      if (want_tiles && c->vdt == TLT_BF16 && !c->tune_head_off) {
-        c->head_cols = std::min(64, n_cols);
-        const size_t rb = sizeof(uint16_t) * (size_t)n_rowsW * c->head_cols;
-        if ((s = dalloc(c, (void **)&c->build_res, rb, "BF16 residuals")) != TLT_OK) goto fail_all;
-        HTRY(hipMemset(c->build_res, 0, rb));
-      }
-      if ((s = device_build_rows(c, d, n_cols)) != TLT_OK) goto fail_all;
+      if (!d->val_is_f64) HTRY(hipMemcpy(c->val, d->val, vsz * nnz, hipMemcpyHostToDevice));
+    } else if ((s = device_build_rows(c, d, n_cols)) != TLT_OK) {
+      goto fail_all;
     }
     if (want_tiles && (s = device_build_tiles(c, tV, n_cols)) != TLT_OK) goto fail_all;
     dfree(c->build_res);
@@ -923,6 +1003,11 @@ tlt_status load_transport(tlt_ctx *c, const tlt_transport_desc *d) {
   if ((s = ensure_P(c, 0)) != TLT_OK) goto fail_all;
   c->loaded = true;
   c->mat_dirty = c->light_dirty = true;
+  c->bf16_plain = c->vdt == TLT_BF16 && !(c->tiles && c->head_cols > 0);
+  if (c->bf16_plain) {
+    c->err = "BF16 storage without the residual words of the coarsest columns";
+    return TLT_W_BF16_NO_RESIDUAL;
+  }
   return TLT_OK;
 fail_all:
   free_all(c);
@@ -930,31 +1015,27 @@ fail_all:
 }
 
 tlt_status set_material(tlt_ctx *c, int n_mat, const double *theta_dev, void *stream) {
+  (void)stream;   // the values are read (and validated) by render, on its stream
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
   if (!c->loaded) return fail(&c->err, TLT_E_STATE, "set_material before load_transport");
   if (n_mat < 1 || !theta_dev) return fail(&c->err, TLT_E_ARG, "need n_mat >= 1 and a pointer");
-  std::vector<double> h((size_t)n_mat * 9);
-  hipStream_t st = (hipStream_t)stream;
-  HIPC(c, hipMemcpyAsync(h.data(), theta_dev, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-  HIPC(c, hipStreamSynchronize(st));
-  bool out_of_range = false;
-  for (int i = 0; i < n_mat * 3; ++i) {
-    const double sa = h[3 * i], ss = h[3 * i + 1], eta = h[3 * i + 2];
-    if (!std::isfinite(sa) || !std::isfinite(ss) || !std::isfinite(eta) || !(sa > 0) || !(ss > 0) ||
-        !(eta >= 1.0))
-      return fail(&c->err, TLT_E_ARG,
-                  "material " + std::to_string(i / 3) + " channel " + std::to_string(i % 3) +
-                      ": need sigma_a > 0, sigma_s' > 0, eta >= 1, all finite");
-    if (c->has_range) {
-      const double v[3] = {sa, ss, eta};
-      for (int p = 0; p < 3; ++p)
-        if (v[p] < c->mat_range[2 * p] || v[p] > c->mat_range[2 * p + 1]) out_of_range = true;
-    }
-  }
   c->theta = theta_dev;
   c->n_mat = n_mat;
   c->mat_dirty = true;
-  if (out_of_range) {
+  return TLT_OK;
+}
+
+tlt_status tlt_material_status(tlt_ctx *c, void *stream) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  HIPC(c, hipStreamSynchronize((hipStream_t)stream));
+  volatile int *f = c->mstat;
+  const int bad = f[0], far = f[1], which = f[2];
+  f[0] = f[1] = f[2] = 0;
+  if (bad)
+    return fail(&c->err, TLT_E_ARG,
+                "material " + std::to_string(which / 3) + " channel " + std::to_string(which % 3) +
+                    ": need sigma_a > 0, sigma_s' > 0, eta >= 1, all finite (its radiance is NaN)");
+  if (far) {
     c->err = "material outside the range of the PCA table";
     return TLT_W_MATERIAL_OUT_OF_RANGE;
   }
@@ -1178,6 +1259,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   const bool use_tiles = c->tiles && !(flags & TLT_PLAIN_ROWS);
   if (save && (s = ensure_V(c)) != TLT_OK) return s;
   Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
+  bool bf16_without_residual = false;
   const bool do_gk = c->mat_dirty || full;
   const bool relight = c->light_dirty || full || !(c->v_valid);
   PrepArgs a = prep_args(c, c->Cs, cols);
@@ -1240,6 +1322,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
     a.ehat2 = c->ehat2;
     a.split = c->vdt == TLT_BF16 ? 1 : 2;
     const bool rows_kernel = !use_tiles && !spatial;
+    bf16_without_residual = c->vdt == TLT_BF16 && !spatial && (rows_kernel || c->bf16_plain);
     if (rows_kernel && (s = ensure_partition(c)) != TLT_OK) return s;
     if (c->n_zero > 0 && rows_kernel) {
       a.B = B;
@@ -1305,6 +1388,10 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (c->view) HIPC(c, launch_view(B, c->view_cos, c->theta, cols, c->N, c->perm, c->fp64, st));
   c->mat_dirty = false;
   c->light_dirty = false;
+  if (bf16_without_residual) {
+    c->err = "BF16 transport product without the residual words of the coarsest columns";
+    return TLT_W_BF16_NO_RESIDUAL;
+  }
   return TLT_OK;
 }
 

@@ -110,6 +110,23 @@ __device__ __forceinline__ uint16_t bf16_residual(double v) {
   return to_bf16((float)(v - (double)hi));
 }
 
+// Caller-given float64 rows (load time): entries e0 .. e0+n of the rows
+// rounded to storage, and for BF16 tiles the residual words of the columns
+// below head_cols, exactly as the device build stores them.
+__global__ void k_quantize_rows(const double *__restrict__ src, const int32_t *__restrict__ col,
+                                void *__restrict__ val, int vdt, int64_t e0, int64_t n,
+                                int64_t n_keep, uint16_t *__restrict__ res, int head_cols) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t e = e0 + i;
+  const double w = src[i];
+  store_value(val, vdt, e, w);
+  if (res != nullptr) {
+    const int j = col[e];
+    if (j < head_cols) res[e / n_keep * head_cols + j] = bf16_residual(w);
+  }
+}
+
 struct Shared {
   double *rn;          // [nr]
   double2 *bs;         // [KG][nr] (basis, slope)
@@ -671,6 +688,14 @@ hipError_t launch_build_sort(const BuildArgs &a, hipStream_t st) {
 }
 
 int build_sort_max() { return 8192; }
+
+hipError_t launch_quantize_rows(const double *src, const int32_t *col, void *val, int vdt, int64_t e0,
+                                int64_t n, int64_t n_keep, uint16_t *res, int head_cols, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_quantize_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, col, val,
+                     vdt, e0, n, n_keep, res, head_cols);
+  return hipGetLastError();
+}
 
 hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st) {
   const size_t lds = sizeof(uint32_t) * (size_t)a.n_words;

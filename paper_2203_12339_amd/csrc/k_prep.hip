@@ -81,6 +81,22 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
   const int m = mc / 3, ch = mc % 3;
   const double sa = a.theta[mc * 3 + 0], ss = a.theta[mc * 3 + 1], eta = a.theta[mc * 3 + 2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // Validation of the material (read here, not on the host): the dipole of
+  // Eq. (4) needs sigma_a, sigma_s' > 0 and the F_dr fit eta >= 1, all
+  // finite.  An invalid channel gets NaN weights (its radiance is NaN, never
+  // silently wrong) and raises the context's invalid flag; a valid one
+  // outside the PCA table's range raises the range flag (still computed).
+  const bool bad = !(isfinite(sa) && isfinite(ss) && isfinite(eta) && sa > 0.0 && ss > 0.0 && eta >= 1.0);
+  const bool far = !bad && a.has_range &&
+                   (sa < a.mat_lo[0] || sa > a.mat_hi[0] || ss < a.mat_lo[1] || ss > a.mat_hi[1] ||
+                    eta < a.mat_lo[2] || eta > a.mat_hi[2]);
+  if (threadIdx.x == 0 && a.mstat != nullptr) {
+    if (bad) {
+      a.mstat[0] = 1;
+      a.mstat[2] = mc;
+    }
+    if (far) a.mstat[1] = 1;
+  }
   // the basis is staged in LDS when it fits the budget (else it is read from
   // memory in place).  With one node per thread (n_r <= 256, K <= 16) the
   // thread's basis values are loaded into registers first and stored after
@@ -137,7 +153,7 @@ __device__ void gk_block(const PrepArgs &a, int mc, double *smem) {
   __syncthreads();
   for (int t = threadIdx.x; t < 4 * a.K; t += 256) {
     const int k = t / 4, qn = t % 4;
-    const double acc = red[t];
+    const double acc = bad ? __builtin_nan("") : red[t];
     if (qn == 0) {
       a.g64[(size_t)mc * a.K + k] = acc;
       for (int o = 0; o < a.cols.n_out; ++o) {

@@ -224,8 +224,11 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 
   // W fragments for step s of this wave's m-tiles, through a buffer
   // resource over the block's values: the step is a scalar offset, the lane
-  // a fixed vector offset, and steps past the block's end read zeros
-  // without touching memory (the descriptor's bound).
+  // a fixed vector offset.  The ring reads up to 2*PD - 1 steps past the
+  // block's end; those steps only ever multiply zero B fragments, and what
+  // they read is finite either way: zeros where the descriptor's bound
+  // clips the access, else the next block's values or, after the last
+  // block, the zeroed slack allocated behind the tile values.
   const int step_bytes = MT * 64 * KPL * TK::VSZ;
   const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
       (void *)((const char *)a.val + vbase * TK::VSZ), (short)0, n_steps * step_bytes, 0x00020000);
@@ -412,6 +415,9 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   a.uc_offset = (int)stage;
   const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
   if (lds > 160 * 1024) return hipErrorInvalidValue;
+  // the ring's reach past the last block must stay inside the slack
+  const size_t step_bytes = (size_t)(a.R / 16) * 64 * TileKind<KIND>::KPL * TileKind<KIND>::VSZ;
+  if ((size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
   TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC>), dim3(hw), dim3(threads), lds, st, a);
   return hipGetLastError();

@@ -47,6 +47,11 @@ struct PrepArgs {
   int gk_stage;            // stage the basis in LDS (K * nr small enough)
   double *g64, *dg64;      // [n_mat][3][K], [n_mat][3][K][3]
   void *gcol;              // [K][Cs] compute precision
+  // material validation: flags [0] invalid, [1] outside the PCA table's
+  // range, [2] an invalid (material, channel) index; host-visible memory
+  int *mstat;
+  int has_range;
+  double mat_lo[3], mat_hi[3];
   // irradiance E = T L and its Haar transform
   int n_tl_blocks;         // n_chunks * Cs/16, or 0
   const void *T;           // [N][t_ld] storage tdt
@@ -113,6 +118,10 @@ struct TileArgs {
 };
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
+// Zeroed bytes allocated after the tile values: the W register ring of the
+// last block reads up to 2*PD - 1 steps (at most 62 KB) past its end.
+// launch_tiles refuses a shape whose ring would reach further.
+constexpr size_t TILE_VAL_SLACK = 128 * 1024;
 
 // Outgoing Fresnel factor (1/pi) F_t(eta, w_o) applied to B in place.
 hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols, int N,
@@ -201,5 +210,10 @@ hipError_t launch_read_probe(const void *buf, int64_t bytes, uint32_t *out, int 
 
 // Storage conversion of float64 values to device storage type.
 hipError_t launch_quantize(const double *src, void *dst, int vdt, int64_t n, hipStream_t st);
+// The same for entries e0 .. e0+n of caller-given rows (col: all columns on
+// the device), writing the BF16 residual words of the columns below
+// head_cols into res [rows][head_cols] when res is not null.
+hipError_t launch_quantize_rows(const double *src, const int32_t *col, void *val, int vdt, int64_t e0,
+                                int64_t n, int64_t n_keep, uint16_t *res, int head_cols, hipStream_t st);
 
 }  // namespace tlt

@@ -23,8 +23,10 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
 OK = 0
 W_MATERIAL_OUT_OF_RANGE = 1
-STATUS = {0: "TLT_OK", 1: "TLT_W_MATERIAL_OUT_OF_RANGE", -1: "TLT_E_ARG", -2: "TLT_E_STATE",
-          -3: "TLT_E_OOM", -4: "TLT_E_HIP", -5: "TLT_E_FORMAT"}
+W_BF16_NO_RESIDUAL = 2
+E_ARG, E_STATE, E_OOM, E_HIP, E_FORMAT = -1, -2, -3, -4, -5
+STATUS = {0: "TLT_OK", 1: "TLT_W_MATERIAL_OUT_OF_RANGE", 2: "TLT_W_BF16_NO_RESIDUAL",
+          -1: "TLT_E_ARG", -2: "TLT_E_STATE", -3: "TLT_E_OOM", -4: "TLT_E_HIP", -5: "TLT_E_FORMAT"}
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
@@ -62,6 +64,7 @@ class TransportDesc(ctypes.Structure):
         ("col", _i32p), ("val", _p), ("position", _f64p), ("transfer", _f64p),
         ("area", _f64p), ("perm", _i32p), ("r_nodes", _f64p), ("basis", _f64p),
         ("mat_range", _f64p), ("layout", ctypes.c_int32), ("tile_vertices", ctypes.c_int32),
+        ("val_is_f64", ctypes.c_int32),
     ]
 
 
@@ -84,7 +87,9 @@ _create = _sig("tlt_create", ctypes.c_int, ctypes.POINTER(_p), ctypes.c_int)
 _destroy = _sig("tlt_destroy", None, _p)
 _last_error = _sig("tlt_last_error", ctypes.c_char_p, _p)
 _load_transport = _sig("load_transport", ctypes.c_int, _p, ctypes.POINTER(TransportDesc))
+_check_transport = _sig("tlt_check_transport", ctypes.c_int, ctypes.POINTER(TransportDesc))
 _set_material = _sig("set_material", ctypes.c_int, _p, ctypes.c_int, _p, _p)
+_material_status = _sig("tlt_material_status", ctypes.c_int, _p, _p)
 _set_lighting = _sig("set_lighting", ctypes.c_int, _p, ctypes.c_int, _p)
 _render = _sig("render", ctypes.c_int, _p, _p, _p, ctypes.c_int)
 _render_backward = _sig("render_backward", ctypes.c_int, _p, _p, _p, _p, _p)
@@ -119,6 +124,7 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
                    ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
 
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
+            "tlt_check_transport", "tlt_material_status",
             "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
             "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
@@ -261,6 +267,64 @@ def spatial_synthesis(n, levels=0):
     return rp, col[:m].astype(np.int64), w[:m]
 
 
+class _Desc:
+    """A TransportDesc with the numpy arrays its pointers refer to kept alive."""
+
+    def __init__(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None,
+                 layout="auto", tile_vertices=0, transfer=None):
+        N = scene["perm"].shape[0]
+        self.N = N
+        self.n_pad = 1 << (N - 1).bit_length()
+        self.vdt = DTYPES[storage]
+        self.n_sh = scene["transfer"].shape[1]
+        self.K = scene["basis"].shape[0]
+        self.wavelet = WAVELET_HAAR if wavelet == "haar" else WAVELET_NONE
+        self.perm = np.ascontiguousarray(scene["perm"], dtype=np.int32)
+        self.arrs = {k: np.ascontiguousarray(scene[k], dtype=np.float64)
+                     for k in ("position", "transfer", "area", "r_nodes", "basis")}
+        self.mr = np.ascontiguousarray(scene.get("mat_range"), dtype=np.float64) \
+            if scene.get("mat_range") is not None else None
+        d = TransportDesc()
+        d.n_vertices, d.n_pad, d.n_sh, d.K = N, self.n_pad, self.n_sh, self.K
+        d.n_r = self.arrs["r_nodes"].shape[0]
+        d.wavelet = self.wavelet
+        d.value_dtype = self.vdt
+        d.transfer_dtype = DTYPES[transfer] if transfer else self.vdt
+        d.n_keep = int(n_keep)
+        d.layout = LAYOUTS[layout]
+        d.tile_vertices = int(tile_vertices)
+        if col is not None:
+            # rows in the storage type's bits (uint16 for BF16/F16), or float64
+            # values that the library rounds to storage itself
+            self.col = np.ascontiguousarray(col, dtype=np.int32)
+            self.val = np.ascontiguousarray(val)
+            if self.val.dtype == np.float64 and self.vdt != F64:
+                d.val_is_f64 = 1
+            else:
+                want = {F64: np.float64, F32: np.float32, BF16: np.uint16, F16: np.uint16}[self.vdt]
+                assert self.val.dtype == want, (self.val.dtype, want)
+            assert self.col.size == N * self.K * int(n_keep) and self.val.size == self.col.size
+            d.col = _ptr(self.col, ctypes.c_int32)
+            d.val = self.val.ctypes.data_as(ctypes.c_void_p)
+        d.position = _ptr(self.arrs["position"], ctypes.c_double)
+        d.transfer = _ptr(self.arrs["transfer"], ctypes.c_double)
+        d.area = _ptr(self.arrs["area"], ctypes.c_double)
+        d.perm = _ptr(self.perm, ctypes.c_int32)
+        d.r_nodes = _ptr(self.arrs["r_nodes"], ctypes.c_double)
+        d.basis = _ptr(self.arrs["basis"], ctypes.c_double)
+        if self.mr is not None:
+            d.mat_range = _ptr(self.mr, ctypes.c_double)
+        self.desc = d
+
+
+def check_transport(scene, n_keep, **kw):
+    """Host-only validation of a transport description (tlt_check_transport):
+    the status load_transport would return for it before any device work;
+    raises TltError on an error."""
+    d = _Desc(scene, n_keep, **kw)
+    return _check(_check_transport(ctypes.byref(d.desc)), None)
+
+
 class Renderer:
     """One library context holding one loaded transport.
 
@@ -277,6 +341,7 @@ class Renderer:
         self._h = h
         self.loaded = False
         self._keep = []
+        self.generation = 0   # counts renders and loads (autograd checks it)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -295,45 +360,23 @@ class Renderer:
     # -- transport --------------------------------------------------------
     def load_transport(self, scene, n_keep, storage="f32", wavelet="haar", col=None, val=None,
                        layout="auto", tile_vertices=0, transfer=None):
-        """transfer: storage of T (default: the storage of W; F64 only with F64)."""
-        N = scene["perm"].shape[0]
-        n_pad = 1 << (N - 1).bit_length()
-        vdt = DTYPES[storage]
-        self.N, self.n_pad = N, n_pad
-        self.n_sh = scene["transfer"].shape[1]
-        self.K = scene["basis"].shape[0]
-        self.fp64 = vdt == F64
+        """transfer: storage of T (default: the storage of W; F64 only with F64).
+        col/val: caller-given rows [N*K, n_keep] (val float64, or the storage
+        type's bits).  Returns the status (TLT_OK or the warning
+        TLT_W_BF16_NO_RESIDUAL)."""
+        d = _Desc(scene, n_keep, storage=storage, wavelet=wavelet, col=col, val=val, layout=layout,
+                  tile_vertices=tile_vertices, transfer=transfer)
+        self.N, self.n_pad = d.N, d.n_pad
+        self.n_sh, self.K = d.n_sh, d.K
+        self.fp64 = d.vdt == F64
         self.storage = storage
-        self.wavelet = WAVELET_HAAR if wavelet == "haar" else WAVELET_NONE
+        self.wavelet = d.wavelet
         self.n_keep = int(n_keep)
-        self.perm = np.ascontiguousarray(scene["perm"], dtype=np.int32)
-        arrs = {k: np.ascontiguousarray(scene[k], dtype=np.float64)
-                for k in ("position", "transfer", "area", "r_nodes", "basis")}
-        mr = np.ascontiguousarray(scene.get("mat_range"), dtype=np.float64) \
-            if scene.get("mat_range") is not None else None
-        d = TransportDesc()
-        d.n_vertices, d.n_pad, d.n_sh, d.K = N, n_pad, self.n_sh, self.K
-        d.n_r = arrs["r_nodes"].shape[0]
-        d.wavelet = self.wavelet
-        d.value_dtype = vdt
-        d.transfer_dtype = DTYPES[transfer] if transfer else vdt
-        d.n_keep = self.n_keep
-        d.layout = LAYOUTS[layout]
-        d.tile_vertices = int(tile_vertices)
-        if col is not None:
-            col = np.ascontiguousarray(col, dtype=np.int32)
-            d.col = _ptr(col, ctypes.c_int32)
-            d.val = val.ctypes.data_as(ctypes.c_void_p)
-        d.position = _ptr(arrs["position"], ctypes.c_double)
-        d.transfer = _ptr(arrs["transfer"], ctypes.c_double)
-        d.area = _ptr(arrs["area"], ctypes.c_double)
-        d.perm = _ptr(self.perm, ctypes.c_int32)
-        d.r_nodes = _ptr(arrs["r_nodes"], ctypes.c_double)
-        d.basis = _ptr(arrs["basis"], ctypes.c_double)
-        if mr is not None:
-            d.mat_range = _ptr(mr, ctypes.c_double)
-        _check(_load_transport(self._h, ctypes.byref(d)), self._h)
+        self.perm = d.perm
+        self.load_status = _check(_load_transport(self._h, ctypes.byref(d.desc)), self._h,
+                                  allow=(OK, W_BF16_NO_RESIDUAL))
         self.loaded = True
+        self.generation += 1
         return self
 
     # -- view -------------------------------------------------------------
@@ -404,13 +447,22 @@ class Renderer:
         return _check(_set_irradiance(self._h, E.shape[0], ctypes.c_void_p(E.data_ptr())), self._h)
 
     def set_material(self, theta):
-        """theta: CUDA float64 tensor [n_mat, 3, 3]. Returns the status."""
+        """theta: CUDA float64 tensor [n_mat, 3, 3] (read and validated on the
+        device by the next render; see material_status)."""
         import torch
         assert theta.is_cuda and theta.dtype == torch.float64 and theta.is_contiguous()
+        assert theta.dim() == 3 and theta.shape[1:] == (3, 3), tuple(theta.shape)
         self._theta = theta
         self.n_mat = theta.shape[0]
         return _check(_set_material(self._h, theta.shape[0], ctypes.c_void_p(theta.data_ptr()),
-                                    _stream()), self._h, allow=(OK, W_MATERIAL_OUT_OF_RANGE))
+                                    _stream()), self._h)
+
+    def material_status(self):
+        """Waits for the current stream; TLT_OK or TLT_W_MATERIAL_OUT_OF_RANGE
+        for the materials rendered since the last call, TltError(TLT_E_ARG)
+        if one was invalid (tlt_material_status)."""
+        return _check(_material_status(self._h, _stream()), self._h,
+                      allow=(OK, W_MATERIAL_OUT_OF_RANGE))
 
     def set_lighting(self, sh):
         """sh: CUDA tensor [n_light, n_sh, 3] (float64 for F64 storage)."""
@@ -435,25 +487,40 @@ class Renderer:
         if out is None:
             out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
                               device=self.torch_device)
+        else:
+            assert out.is_cuda and out.dtype == self.out_dtype() and out.is_contiguous()
+            assert tuple(out.shape) == (self.n_out, self.N, 3), tuple(out.shape)
         flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0) | \
             (PLAIN_ROWS if plain else 0) | (FOLDED_LIGHTING if folded else 0) | \
             (SPATIAL if spatial else 0)
-        _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags), self._h)
+        self.render_status = _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags),
+                                    self._h, allow=(OK, W_BF16_NO_RESIDUAL))
+        self.generation += 1
         return out
 
     def render_raw(self, out_ptr: int, flags: int):
         """Render into a raw device pointer (for graph capture and timing)."""
-        return _check(_render(self._h, ctypes.c_void_p(out_ptr), _stream(), flags), self._h)
+        self.generation += 1
+        return _check(_render(self._h, ctypes.c_void_p(out_ptr), _stream(), flags), self._h,
+                      allow=(OK, W_BF16_NO_RESIDUAL))
 
     def render_backward(self, dB, dSH=None, dTheta=None):
         import torch
+        assert dB.is_cuda and dB.dtype == self.out_dtype(), (dB.dtype, self.out_dtype())
+        assert tuple(dB.shape) == (self.n_out, self.N, 3), (tuple(dB.shape), (self.n_out, self.N, 3))
         dB = dB.contiguous()
         if dSH is None:
             dSH = torch.empty((self.n_light, self.n_sh, 3), dtype=self.out_dtype(),
                               device=self.torch_device)
+        else:
+            assert dSH.is_cuda and dSH.dtype == self.out_dtype() and dSH.is_contiguous()
+            assert tuple(dSH.shape) == (self.n_light, self.n_sh, 3), tuple(dSH.shape)
         if dTheta is None:
             dTheta = torch.empty((self.n_mat, 3, 3), dtype=torch.float64,
                                  device=self.torch_device)
+        else:
+            assert dTheta.is_cuda and dTheta.dtype == torch.float64 and dTheta.is_contiguous()
+            assert tuple(dTheta.shape) == (self.n_mat, 3, 3), tuple(dTheta.shape)
         _check(_render_backward(self._h, ctypes.c_void_p(dB.data_ptr()),
                                 ctypes.c_void_p(dSH.data_ptr()),
                                 ctypes.c_void_p(dTheta.data_ptr()), _stream()), self._h)

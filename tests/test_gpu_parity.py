@@ -469,16 +469,27 @@ def test_error_paths_on_device():
     with pytest.raises(tlt.TltError) as ei:
         r.render_raw(out.data_ptr(), 0)
     assert ei.value.status == -2                      # not set yet
+    # materials are validated on the device by the render that reads them:
+    # an invalid channel renders NaN and is reported by material_status
+    r.set_lighting(dev_tensor(synth.make_lighting(w), "f32"))
     bad = synth.make_materials(w)
-    bad[0, 1, 0] = -1.0
+    bad[0, 1, 0] = -1.0                               # sigma_a <= 0 in channel 1
+    assert r.set_material(dev_tensor(bad, "f64")) == tlt.OK
+    Bb = r.render(force=True).cpu().numpy()
+    assert np.all(np.isnan(Bb[:, :, 1])) and np.all(np.isfinite(Bb[:, :, [0, 2]]))
     with pytest.raises(tlt.TltError) as ei:
-        r.set_material(dev_tensor(bad, "f64"))
-    assert ei.value.status == -1
+        r.material_status()
+    assert ei.value.status == -1 and "material 0 channel 1" in str(ei.value)
+    assert r.material_status() == tlt.OK              # reported once, then cleared
     far = synth.make_materials(w)
     far[0, 0, 0] = 0.5                                # sigma_a outside the PCA table
-    assert r.set_material(dev_tensor(far, "f64")) == tlt.W_MATERIAL_OUT_OF_RANGE
-    r.set_lighting(dev_tensor(synth.make_lighting(w), "f32"))
+    r.set_material(dev_tensor(far, "f64"))
+    Bf = r.render().cpu().numpy()
+    assert np.all(np.isfinite(Bf))
+    assert r.material_status() == tlt.W_MATERIAL_OUT_OF_RANGE
+    r.set_material(dev_tensor(synth.make_materials(w), "f64"))
     r.render()
+    assert r.material_status() == tlt.OK
     with pytest.raises(tlt.TltError) as ei:
         r.render_backward(torch.zeros((1, w.n_vertices, 3), device="cuda:0"))
     assert ei.value.status == -2                      # forward did not save
