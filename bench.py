@@ -170,7 +170,7 @@ def per_step_timing(args, r, step, B):
     sink = torch.empty((), dtype=torch.float32, device=B.device)
     r.profile(True)
     out["cold"] = _quantiles(bracketed(step, pre=lambda i: torch.sum(scratch, dim=0, out=sink)))
-    ms_tr, n_tr = r.profile_read("transport")
+    ms_tr, n_tr = r.profile_read("combine" if args.material_edit else "transport")
     r.profile(False)
     out["cold"]["evict_mib"] = args.evict_mib
     out["cold"]["transport_us"] = round(1e3 * ms_tr / max(n_tr, 1), 2)
@@ -310,7 +310,7 @@ def main():
                     help="relight through the folded lighting transport B = sum_k g_k P_k L")
     ap.add_argument("--material-edit", action="store_true",
                     help="time material edits: each step sets one of two material sets and "
-                         "renders from the saved per-term transport (Steps 3 and 4 only)")
+                         "renders from the kept per-term transport (Steps 3 and 4 only)")
     ap.add_argument("--spatial", type=float, default=0.0, metavar="ENERGY",
                     help="render through the spatially compressed transport (CDF 9/7 over the "
                          "output vertices) keeping this fraction of the coefficient energy")
@@ -397,12 +397,12 @@ def main():
             r.render_backward(dB, dSH, dTh)
 
     if args.material_edit:
-        # one full render saves v_k; every step then edits the material --
+        # one full render keeps v_k; every step then edits the material --
         # new values written into the material buffer on the device, then
         # set_material (no host round trip: the values are validated by the
         # weights kernel) -- and renders: the weights and the combine over the
-        # saved v_k (Steps 3 and 4 only).  The step is graph-capturable.
-        r.render_raw(B.data_ptr(), flags | tlt.SAVE_FOR_BACKWARD)
+        # kept v_k (Steps 3 and 4 only).  The step is graph-capturable.
+        r.render_raw(B.data_ptr(), flags | tlt.KEEP_TERMS)
         mats = [tt.clone(), torch.tensor(synth.make_materials(w, seed=4242), dtype=torch.float64, device=dev)]
         edit = [0]
 
@@ -437,7 +437,7 @@ def main():
     r.profile(False)
     if args.material_edit:
         # back to the first material set, so the accuracy check below sees
-        # a material edit rendered through the saved v_k
+        # a material edit rendered through the kept v_k
         tt.copy_(mats[0])
         r.set_material(tt)
         r.render_raw(B.data_ptr(), tlt.PLAIN_ROWS if args.plain else 0)
@@ -464,7 +464,7 @@ def main():
         kernel, traffic = "k_sp_rows", None
         flops = 2.0 * sp["nnz"] * C
     elif args.material_edit:
-        # saved v_k (K x N x Cs) read once, B written once
+        # kept v_k (K x N x Cs) read once, B written once
         cs = (C + 15) // 16 * 16
         alg_bytes = w.K * w.n_vertices * cs * esz + w.n_vertices * C * esz
         kernel, traffic = "k_combine", None
@@ -477,12 +477,10 @@ def main():
         flops = 2.0 * w.K * w.n_vertices * w.n_sh * C
     else:
         # kept (index, value) entries read once, Ehat read once, B written
-        # once, and with the adjoint the per-term v_k written once
+        # once (the adjoint needs nothing saved by the forward pass)
         alg_bytes = nnz * (4 + vsz) + n_rows * C * esz + w.n_vertices * C * esz
-        if args.backward:
-            alg_bytes += w.K * w.n_vertices * C * esz
         kernel = "k_stream" if args.plain else "k_tiles"
-        traffic = None if args.plain or args.backward else stored_traffic(w.name, C)
+        traffic = None if args.plain else stored_traffic(w.name, C)
         flops = 2.0 * nnz * C
     avg_s = ms_tr / max(n_tr, 1) * 1e-3
     warm = {"kernel_us": round(avg_s * 1e6, 2), "achieved": round(alg_bytes / avg_s / 1e9, 1),
@@ -514,10 +512,10 @@ def main():
         roofline["cold"] = cold
     roofline_adj = None
     if args.backward and stage_ms["adjoint"][1] > 0:
-        # saved v_k and the lighting-transfer product P read once, the
-        # upstream gradient read once (outputs are a few KB)
+        # the lighting-transfer product P read once and the upstream
+        # gradient read once (partial sums and outputs are a few MB)
         psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
-        adj_bytes = (w.K * w.n_vertices * C + w.K * w.n_vertices * psh + w.n_vertices * C) * esz
+        adj_bytes = (w.K * w.n_vertices * psh + w.n_vertices * C) * esz
         adj_s = stage_ms["adjoint"][0] / stage_ms["adjoint"][1] * 1e-3
         roofline_adj = {"bound": "hbm", "achieved": round(adj_bytes / adj_s / 1e9, 1), "peak": HBM_PEAK_GBS,
                         "unit": "GB/s", "frac": round(adj_bytes / adj_s / 1e9 / HBM_PEAK_GBS, 4),

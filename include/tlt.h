@@ -55,11 +55,12 @@ typedef enum {
 enum { TLT_F64 = 0, TLT_F32 = 1, TLT_BF16 = 2, TLT_F16 = 3 };
 enum { TLT_WAVELET_NONE = 0, TLT_WAVELET_HAAR = 1 };
 enum {
-  TLT_SAVE_FOR_BACKWARD = 1, /* keep v_k[o,c] for render_backward */
+  TLT_SAVE_FOR_BACKWARD = 1, /* render_backward may differentiate this render (no extra work) */
   TLT_FORCE_FULL = 2,        /* recompute every stage, ignoring dirty flags */
   TLT_PLAIN_ROWS = 4,        /* use the (column, value) row kernel even when tiles exist */
   TLT_FOLDED_LIGHTING = 8,   /* relight through P_k = W_k H (A o T): B = sum_k g_k P_k L */
-  TLT_SPATIAL = 16           /* render through the spatially compressed transport (load_spatial) */
+  TLT_SPATIAL = 16,          /* render through the spatially compressed transport (load_spatial) */
+  TLT_KEEP_TERMS = 32        /* keep v_k[v,c] so a material-only edit reruns Steps 3-4 only */
 };
 enum { TLT_LAYOUT_AUTO = 0, TLT_LAYOUT_ROWS = 1, TLT_LAYOUT_TILES = 2 };
 
@@ -290,18 +291,23 @@ tlt_status set_view(tlt_ctx *ctx, const double *eye, const double *position, con
 /*
  * Renders B [n_out][N][3] (original vertex order, float64 for an F64
  * transport else float32) into caller-owned device memory on hip_stream.
- * Recomputes only what changed since the last render (a material change
- * reruns Steps 3-4 of Sec. 4 only) unless TLT_FORCE_FULL.  With
- * TLT_SAVE_FOR_BACKWARD keeps v_k[o,c] for render_backward.
+ * Recomputes only what changed since the last render unless TLT_FORCE_FULL.
+ * TLT_KEEP_TERMS keeps the per-term transport v_k[v,c] = (W_k Ehat)[o,c]
+ * (v = perm[o]; K*N*C values in library memory), so that a following render
+ * after a material-only change (set_material, no set_lighting) reruns Steps 3
+ * and 4 of Sec. 4 only: the weights and B = sum_k g_k v_k.  Without a kept
+ * v_k every render runs the transport.  TLT_SAVE_FOR_BACKWARD marks the
+ * render as the one render_backward differentiates; it costs nothing here.
  * TLT_FOLDED_LIGHTING renders through the lighting transport folded at load,
  * P_k = W_k H (A o T) (the SH-lighting path of Eq. 14): B = sum_k g_k P_k L,
  * equal to the wavelet transport of the same kept coefficients up to
  * float32 rounding, reading K*N*Psh values instead of the transport
- * (incompatible with TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS: TLT_E_ARG).
+ * (incompatible with TLT_KEEP_TERMS and TLT_PLAIN_ROWS: TLT_E_ARG).
  * TLT_SPATIAL renders through the spatially compressed transport of
  * load_spatial (Eq. 10, Steps 2, 4 and 5 of Sec. 4), recomputing every stage;
  * TLT_E_STATE without load_spatial, TLT_E_ARG combined with
- * TLT_SAVE_FOR_BACKWARD, TLT_PLAIN_ROWS or TLT_FOLDED_LIGHTING.
+ * TLT_SAVE_FOR_BACKWARD, TLT_KEEP_TERMS, TLT_PLAIN_ROWS or
+ * TLT_FOLDED_LIGHTING.
  * TLT_E_STATE before load_transport / set_material / set_lighting.
  * Warning TLT_W_BF16_NO_RESIDUAL (rendered): the product of a BF16
  * transport ran without residual words -- TLT_PLAIN_ROWS (the row kernel
@@ -390,11 +396,19 @@ tlt_status tlt_read_spatial(tlt_ctx *ctx, int64_t u0, int64_t n_u, int64_t *rowp
 
 /*
  * Adjoint of the last render (which must have used TLT_SAVE_FOR_BACKWARD,
- * else TLT_E_STATE).  dB_dev [n_out][N][3] upstream gradient (precision of
- * B).  Writes dSH_dev [n_light][n_sh][3] (precision of B) and dTheta_dev
- * [n_mat][3][3] float64, both device memory, overwritten (not accumulated).
- * The lighting gradient is the exact transpose of the transport:
- * sum_k g_k (W_k G)^T dB with G = Haar(pad(A o T)) precomputed at load.
+ * with no set_lighting / set_material since, else TLT_E_STATE; also
+ * TLT_E_STATE after set_irradiance or with a view set).  dB_dev
+ * [n_out][N][3] upstream gradient (precision of B).  Writes dSH_dev
+ * [n_light][n_sh][3] (precision of B) and dTheta_dev [n_mat][3][3] float64,
+ * both device memory, overwritten (not accumulated).  Steps 1-4 of Sec. 4 are
+ * linear in the lighting and in the weights, and with the lighting-transfer
+ * product P_k = W_k G, G = Haar(pad(A o T)) built at load, the per-term
+ * transport is v_k = P_k L.  Both gradients follow from Z_k = P_k^T dB:
+ *   dLoss/dg_k[c] = sum_lm L[lm,c] Z_k[lm,c],  dSH[lm,c] = sum_k g_k[c] Z_k[lm,c]
+ * and dTheta = sum dLoss/dg_k * dg_k/dtheta (Eq. 4 differentiated in float64).
+ * The lighting buffer of set_lighting is read again here, on hip_stream: it
+ * must still hold the rendered values.  The first call (and a call with more
+ * columns than before) allocates the library's partial-sum buffer.
  */
 tlt_status render_backward(tlt_ctx *ctx, const void *dB_dev, void *dSH_dev,
                            double *dTheta_dev, void *hip_stream);

@@ -11,11 +11,15 @@ class TranslucentRender(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, renderer, sh, theta):
-        renderer.set_lighting(sh.detach().contiguous())
+        sh_in = sh.detach().contiguous()
+        renderer.set_lighting(sh_in)
         renderer.set_material(theta.detach().contiguous())
         B = renderer.render(save=True)
         ctx.renderer = renderer
         ctx.generation = renderer.generation
+        # the adjoint reads the lighting buffer again: saving the inputs makes
+        # autograd refuse a backward after they were modified in place
+        ctx.save_for_backward(sh, theta)
         return B
 
     @staticmethod
@@ -25,6 +29,7 @@ class TranslucentRender(torch.autograd.Function):
         if ctx.renderer.generation != ctx.generation:
             raise RuntimeError("the renderer rendered again after this forward; backward would use "
                                "the state of the later render")
+        ctx.saved_tensors  # raises if sh or theta changed in place since forward
         dSH, dTheta = ctx.renderer.render_backward(dB.contiguous())
         return None, dSH, dTheta
 

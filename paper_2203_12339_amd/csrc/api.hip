@@ -60,7 +60,8 @@ struct tlt_ctx {
   uint16_t *build_res = nullptr;
   int head_cols = 0;
 
-  // lighting-transfer product for the adjoint: P[k][o][Psh] = W_k G
+  // lighting-transfer product P[k][v][Psh] = W_k G, rows in original vertex
+  // order (folded lighting and the adjoint)
   bool have_P = false;
   int Psh = 0, Gs = 0;
   void *P = nullptr;
@@ -92,7 +93,9 @@ struct tlt_ctx {
   size_t adj_bytes = 0;
   void *fold = nullptr;   // folded lighting weights [K*Psh][Cs]
   size_t fold_bytes = 0;
-  bool v_valid = false;   // V holds v_k of the current lighting
+  bool v_valid = false;   // V holds v_k of the current lighting (TLT_KEEP_TERMS)
+  bool bwd_valid = false; // the last render was made with TLT_SAVE_FOR_BACKWARD
+  void *scratch_dev = nullptr;   // this device's copy of the static adjoint scratch
   int n_chunks = 0, ch_rows = 0;
 
   // block-dense tiles (see tlt.h): offsets, union columns, values
@@ -205,6 +208,7 @@ void free_columns(tlt_ctx *c) {
   c->C = c->Cs = c->n_out = 0;
   c->buf_nlight = c->buf_nmat = -1;
   c->v_valid = false;
+  c->bwd_valid = false;
 }
 
 void free_spatial(tlt_ctx *c) {
@@ -1051,6 +1055,7 @@ tlt_status set_lighting(tlt_ctx *c, int n_light, const void *sh_dev) {
   c->n_light = n_light;
   c->light_dirty = true;
   c->v_valid = false;
+  c->bwd_valid = false;
   return TLT_OK;
 }
 
@@ -1063,6 +1068,7 @@ tlt_status set_irradiance(tlt_ctx *c, int n_light, const void *E_dev) {
   c->n_light = n_light;
   c->light_dirty = true;
   c->v_valid = false;
+  c->bwd_valid = false;
   return TLT_OK;
 }
 
@@ -1240,24 +1246,29 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (c->n_light != c->n_mat && c->n_light != 1 && c->n_mat != 1)
     return fail(&c->err, TLT_E_ARG, "n_light and n_mat must match or one must be 1");
   if (flags & ~(TLT_SAVE_FOR_BACKWARD | TLT_FORCE_FULL | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING |
-                TLT_SPATIAL))
+                TLT_SPATIAL | TLT_KEEP_TERMS))
     return fail(&c->err, TLT_E_ARG, "unknown flags");
   const bool spatial = flags & TLT_SPATIAL;
-  if (spatial && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING)))
+  if (spatial && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_KEEP_TERMS | TLT_PLAIN_ROWS | TLT_FOLDED_LIGHTING)))
     return fail(&c->err, TLT_E_ARG,
-                "TLT_SPATIAL excludes TLT_SAVE_FOR_BACKWARD, TLT_PLAIN_ROWS and TLT_FOLDED_LIGHTING");
+                "TLT_SPATIAL excludes TLT_SAVE_FOR_BACKWARD, TLT_KEEP_TERMS, TLT_PLAIN_ROWS and "
+                "TLT_FOLDED_LIGHTING");
   if (spatial && !c->spatial) return fail(&c->err, TLT_E_STATE, "TLT_SPATIAL before load_spatial");
-  if ((flags & TLT_FOLDED_LIGHTING) && (flags & (TLT_SAVE_FOR_BACKWARD | TLT_PLAIN_ROWS)))
-    return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING excludes TLT_SAVE_FOR_BACKWARD and TLT_PLAIN_ROWS");
+  if ((flags & TLT_FOLDED_LIGHTING) && (flags & (TLT_KEEP_TERMS | TLT_PLAIN_ROWS)))
+    return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING excludes TLT_KEEP_TERMS and TLT_PLAIN_ROWS");
   if ((flags & TLT_FOLDED_LIGHTING) && c->use_E)
     return fail(&c->err, TLT_E_ARG, "TLT_FOLDED_LIGHTING needs SH lighting, not a supplied irradiance");
   hipStream_t st = (hipStream_t)stream;
   tlt_status s;
   if ((s = ensure_columns(c)) != TLT_OK) return s;
   const bool save = flags & TLT_SAVE_FOR_BACKWARD;
+  const bool keep = flags & TLT_KEEP_TERMS;
   const bool full = flags & TLT_FORCE_FULL;
   const bool use_tiles = c->tiles && !(flags & TLT_PLAIN_ROWS);
-  if (save && (s = ensure_V(c)) != TLT_OK) return s;
+  if (keep && (s = ensure_V(c)) != TLT_OK) return s;
+  // the adjoint differentiates this render: it reads P, the weights and
+  // the lighting buffer of this render (no extra writes here)
+  c->bwd_valid = false;
   Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
   bool bf16_without_residual = false;
   const bool do_gk = c->mat_dirty || full;
@@ -1285,17 +1296,18 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
       c->fold_bytes = need;
     }
     StageTimer t(c, 2, st);
-    HIPC(c, launch_folded(c->P, c->Psh, c->n_sh, c->K, c->gcol, c->Cs, c->sh, cols, c->N, c->perm, B,
-                          c->fp64, c->fold, st));
+    HIPC(c, launch_folded(c->P, c->Psh, c->n_sh, c->K, c->gcol, c->Cs, c->sh, cols, c->N, B, c->fp64,
+                          c->fold, st));
     c->v_valid = false;
   } else if (!relight && c->V && !spatial) {
-    // material-only edit: reuse the saved per-term transport v_k
+    // material-only edit: reuse the per-term transport v_k kept by the last
+    // full render (TLT_KEEP_TERMS)
     if (do_gk) {
       StageTimer t(c, 0, st);
       HIPC(c, launch_prep(a, st));
     }
     StageTimer t(c, 4, st);
-    HIPC(c, launch_combine(c->V, c->Cs, c->gcol, c->K, c->N, c->C, c->perm, B, c->fp64, st));
+    HIPC(c, launch_combine(c->V, c->Cs, c->gcol, c->K, c->N, c->C, B, c->fp64, st));
   } else {
     a.n_tl_blocks = c->n_chunks * (c->Cs / 16);
     if (c->use_E) {
@@ -1371,11 +1383,11 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
         HIPC(c, launch_spatial_rows(spa, c->fp64, st));
       } else if (use_tiles) {
         HIPC(c, launch_tiles(tile_args(c, c->ehat, c->ehat2, c->Cs, c->C, c->gcol, B,
-                                       save ? c->V : nullptr, c->Cs),
+                                       keep ? c->V : nullptr, c->Cs),
                              c->vdt, st));
       } else {
         if ((s = ensure_partition(c)) != TLT_OK) return s;
-        StreamArgs sa = stream_args(c, c->ehat, c->Cs, c->C, c->gcol, B, save ? c->V : nullptr, c->Cs);
+        StreamArgs sa = stream_args(c, c->ehat, c->Cs, c->C, c->gcol, B, keep ? c->V : nullptr, c->Cs);
         HIPC(c, launch_stream(sa, c->vdt, c->fp64, c->cpl, st));
       }
     }
@@ -1383,8 +1395,9 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
       StageTimer t(c, 5, st);
       HIPC(c, launch_spatial_synthesis(spa, c->fp64, st));
     }
-    c->v_valid = save && !spatial;
+    c->v_valid = keep && !spatial;
   }
+  c->bwd_valid = save && !spatial && !c->use_E;
   if (c->view) HIPC(c, launch_view(B, c->view_cos, c->theta, cols, c->N, c->perm, c->fp64, st));
   c->mat_dirty = false;
   c->light_dirty = false;
@@ -1395,9 +1408,10 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   return TLT_OK;
 }
 
-tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta, void *stream) {
+// Checks of the adjoint entry points.
+static tlt_status backward_check(tlt_ctx *c, const void *dB, const void *dSH, const double *dTheta) {
   if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
-  if (!c->loaded || !c->v_valid || !c->have_P || c->mat_dirty || c->light_dirty)
+  if (!c->loaded || !c->bwd_valid || !c->have_P || c->mat_dirty || c->light_dirty)
     return fail(&c->err, TLT_E_STATE,
                 "render_backward needs a render with TLT_SAVE_FOR_BACKWARD of the current inputs");
   if (c->use_E)
@@ -1405,20 +1419,29 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
   if (c->view)
     return fail(&c->err, TLT_E_STATE, "render_backward is for the radiance without the view factor");
   if (!dB || !dSH || !dTheta) return fail(&c->err, TLT_E_ARG, "NULL gradient pointer");
-  hipStream_t st = (hipStream_t)stream;
-  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->Cs, c->fp64);
+  return TLT_OK;
+}
+
+static tlt_status backward_launch(tlt_ctx *c, const void *dB, void *dSH, double *dTheta,
+                                  void *scratch_ptr, size_t scratch_bytes, hipStream_t st) {
+  Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
+  StageTimer t(c, 3, st);
+  HIPC(c, launch_adjoint(dB, c->P, c->Psh, c->gcol, c->Cs, c->sh, c->dg64, c->N, c->K, c->n_sh, cols,
+                         c->fp64, scratch_ptr, scratch_bytes, dSH, dTheta, st));
+  return TLT_OK;
+}
+
+tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta, void *stream) {
+  tlt_status s = backward_check(c, dB, dSH, dTheta);
+  if (s != TLT_OK) return s;
+  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->fp64);
   if (c->adj_bytes < need) {
     dfree(c->adj);
     c->adj_bytes = 0;
-    tlt_status s = dalloc(c, &c->adj, need, "adjoint partials");
-    if (s != TLT_OK) return s;
+    if ((s = dalloc(c, &c->adj, need, "adjoint partials")) != TLT_OK) return s;
     c->adj_bytes = need;
   }
-  Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
-  StageTimer t(c, 3, st);
-  HIPC(c, launch_adjoint(dB, c->V, c->Cs, c->P, c->Psh, c->gcol, c->dg64, c->perm, c->N, c->K,
-                         c->n_sh, cols, c->fp64, c->adj, c->adj_bytes, dSH, dTheta, st));
-  return TLT_OK;
+  return backward_launch(c, dB, dSH, dTheta, c->adj, c->adj_bytes, (hipStream_t)stream);
 }
 
 tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {

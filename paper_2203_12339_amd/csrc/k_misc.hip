@@ -6,59 +6,73 @@
 namespace tlt {
 
 // Material-only update (Steps 3-4 of Sec. 4): B = sum_k g_k v_k from the
-// v_k saved by the last full render.  One thread per (vertex, column).
+// v_k kept by the last full render, [N][K][Cs] with vertices in original
+// order (so the output rows are written where they are read).  One thread per (vertex,
+// column).
 template <typename CT>
 __global__ __launch_bounds__(256) void k_combine(const CT *__restrict__ V, int Cs,
                                                  const CT *__restrict__ gcol, int K, int N, int C,
-                                                 const int32_t *__restrict__ perm,
                                                  CT *__restrict__ B) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)N * C) return;
-  const int o = (int)(t / C), c = (int)(t - (int64_t)o * C);
+  const int v = (int)(t / C), c = (int)(t - (int64_t)v * C);
   CT s = 0;
-  for (int k = 0; k < K; ++k) s = fma(gcol[(size_t)k * Cs + c], V[((int64_t)k * N + o) * Cs + c], s);
+  for (int k = 0; k < K; ++k) s = fma(gcol[(size_t)k * Cs + c], V[((int64_t)v * K + k) * Cs + c], s);
   const int q = c / 3, ch = c - 3 * q;
-  B[((int64_t)q * N + perm[o]) * 3 + ch] = s;
+  B[((int64_t)q * N + v) * 3 + ch] = s;
 }
 
-// Float32 form: one thread per vertex and four consecutive columns (Cs is a
-// multiple of 16), the KT <= 16 terms' 16-byte loads of v_k all issued
-// before the sums, so each thread keeps KT loads in flight.
+// Float32 form over tiles of CMB_V vertices x CMB_W columns (16 output
+// sets; Cs is a multiple of 16 and CMB_W of 3 and 16): every thread takes
+// CMB_Q column quads of the tile and issues the 16-byte loads of all KT <= 16
+// terms before the sums; the sums go to LDS, and the tile's rows of each
+// output set are then written as one contiguous run of 3 * CMB_V floats.
+constexpr int CMB_V = 64, CMB_W = 48, CMB_Q = CMB_V * (CMB_W / 4) / 256;
+
 template <int KT>
 __global__ __launch_bounds__(256) void k_combine4(const float *__restrict__ V, int Cs,
                                                   const float *__restrict__ gcol, int K, int N, int C,
-                                                  const int32_t *__restrict__ perm,
                                                   float *__restrict__ B) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int nq = Cs / 4;
-  if (t >= (int64_t)N * nq) return;
-  const int o = (int)(t / nq), c0 = 4 * (int)(t - (int64_t)o * nq);
-  if (c0 >= C) return;
-  float4 v[KT], g[KT];
+  __shared__ float bs[CMB_W][CMB_V + 1];
+  const int t = threadIdx.x;
+  const int v0 = blockIdx.x * CMB_V, cg0 = blockIdx.y * CMB_W;
+  float4 v[CMB_Q][KT];
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    const int kk = min(k, K - 1);
-    v[k] = *reinterpret_cast<const float4 *>(V + ((int64_t)kk * N + o) * Cs + c0);
-    g[k] = *reinterpret_cast<const float4 *>(gcol + (size_t)kk * Cs + c0);
+  for (int i = 0; i < CMB_Q; ++i) {
+    const int item = t + 256 * i;                 // (vertex, quad) of the tile
+    const int vl = item / (CMB_W / 4), c0 = cg0 + 4 * (item % (CMB_W / 4));
+    const int vtx = min(v0 + vl, N - 1), cc = min(c0, Cs - 4);
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+      v[i][k] = *reinterpret_cast<const float4 *>(V + ((int64_t)vtx * K + min(k, K - 1)) * Cs + cc);
   }
-  float s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < K) {
-      s[0] = fmaf(g[k].x, v[k].x, s[0]);
-      s[1] = fmaf(g[k].y, v[k].y, s[1]);
-      s[2] = fmaf(g[k].z, v[k].z, s[2]);
-      s[3] = fmaf(g[k].w, v[k].w, s[3]);
+  for (int i = 0; i < CMB_Q; ++i) {
+    const int item = t + 256 * i;
+    const int vl = item / (CMB_W / 4), ql = item % (CMB_W / 4), c0 = cg0 + 4 * ql;
+    const int cc = min(c0, Cs - 4);
+    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      if (k < K) {
+        const float4 g = *reinterpret_cast<const float4 *>(gcol + (size_t)k * Cs + cc);
+        s[0] = fmaf(g.x, v[i][k].x, s[0]);
+        s[1] = fmaf(g.y, v[i][k].y, s[1]);
+        s[2] = fmaf(g.z, v[i][k].z, s[2]);
+        s[3] = fmaf(g.w, v[i][k].w, s[3]);
+      }
     }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bs[4 * ql + j][vl] = s[j];
   }
-  const int64_t po = perm[o];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = c0 + j;
-    if (c < C) {
-      const int q = c / 3, ch = c - 3 * q;
-      B[((int64_t)q * N + po) * 3 + ch] = s[j];
-    }
+  __syncthreads();
+  // set q of the tile: B[q][v0 .. v0 + CMB_V)[0..2], contiguous
+  const int nv = min(CMB_V, N - v0);
+  for (int i = t; i < (CMB_W / 3) * 3 * CMB_V; i += 256) {
+    const int ql = i / (3 * CMB_V), r = i - ql * 3 * CMB_V;
+    const int vl = r / 3, ch = r - 3 * vl;
+    const int c = cg0 + 3 * ql + ch;
+    if (vl < nv && c < C) B[((int64_t)(c / 3) * N + v0) * 3 + r] = bs[3 * ql + ch][vl];
   }
 }
 
@@ -102,34 +116,32 @@ hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols
   return hipGetLastError();
 }
 
-hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
-                          const int32_t *perm, void *B, bool fp64, hipStream_t st) {
+hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C, void *B,
+                          bool fp64, hipStream_t st) {
   const int64_t n = (int64_t)N * C;
   const unsigned blocks = (unsigned)((n + 255) / 256);
   if (fp64)
     TLT_LAUNCH(k_combine<double>, dim3(blocks), dim3(256), 0, st, (const double *)V, Cs,
-                       (const double *)gcol, K, N, C, perm, (double *)B);
+               (const double *)gcol, K, N, C, (double *)B);
   else if (Cs % 16 == 0 && K <= 16) {
-    const int64_t n4 = (int64_t)N * (Cs / 4);
-    const unsigned b4 = (unsigned)((n4 + 255) / 256);
+    const dim3 g((N + CMB_V - 1) / CMB_V, (C + CMB_W - 1) / CMB_W);
+    const float *Vf = (const float *)V, *gf = (const float *)gcol;
     if (K <= 4)
-      TLT_LAUNCH(k_combine4<4>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol, K,
-                 N, C, perm, (float *)B);
+      TLT_LAUNCH(k_combine4<4>, g, dim3(256), 0, st, Vf, Cs, gf, K, N, C, (float *)B);
     else if (K <= 8)
-      TLT_LAUNCH(k_combine4<8>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol, K,
-                 N, C, perm, (float *)B);
+      TLT_LAUNCH(k_combine4<8>, g, dim3(256), 0, st, Vf, Cs, gf, K, N, C, (float *)B);
     else
-      TLT_LAUNCH(k_combine4<16>, dim3(b4), dim3(256), 0, st, (const float *)V, Cs, (const float *)gcol,
-                 K, N, C, perm, (float *)B);
+      TLT_LAUNCH(k_combine4<16>, g, dim3(256), 0, st, Vf, Cs, gf, K, N, C, (float *)B);
   } else
     TLT_LAUNCH(k_combine<float>, dim3(blocks), dim3(256), 0, st, (const float *)V, Cs,
-                       (const float *)gcol, K, N, C, perm, (float *)B);
+               (const float *)gcol, K, N, C, (float *)B);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Folded lighting transport (Eq. 14, the SH lighting path): with
-// P_k = W_k H (A o T) (built at load, [K][N][Psh], Morton rows),
+// P_k = W_k H (A o T) (built at load, [N][K][Psh] with vertices in original
+// order, so row o of the product is output vertex o),
 //   B[o, c] = sum_k g_k[c] sum_lm P_k[o, lm] L[light(c)][lm][ch(c)],
 // one matrix product over the contraction index (k, lm):
 //   B[o, c] = sum_(k,lm) P[o, (k,lm)] Lg[(k,lm), c],  Lg = g_k[c] L[lm][c].
@@ -172,7 +184,6 @@ __global__ __launch_bounds__(256) void k_fold_weights(const CT *__restrict__ gco
 template <typename CT, int NTN, int MS, int RT>
 __global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Psh, int K,
                                                 const CT *__restrict__ Lg, int Cs, int C, int N,
-                                                const int32_t *__restrict__ perm,
                                                 CT *__restrict__ B) {
   typedef typename MfmaOut<CT>::V4 V4;
   const int t = threadIdx.x;
@@ -190,13 +201,13 @@ __global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Ps
   for (int r = 0; r < RT; ++r) {
     const int o = (tile0 + r) * 16 + li;
     rok[r] = o < N;
-    prow[r] = P + (int64_t)min(o, N - 1) * Psh;
+    prow[r] = P + (int64_t)min(o, N - 1) * K * Psh;
   }
   int bcol[NTN];
 #pragma unroll
   for (int nt = 0; nt < NTN; ++nt) bcol[nt] = min(cg0 + nt * 16 + li, Cs - 1);
   for (int k = 0; k < K; ++k) {
-    const int64_t koff = (int64_t)k * N * Psh;
+    const int64_t koff = (int64_t)k * Psh;
     CT av[RT][MS];
     CT bv[MS][NTN];
 #pragma unroll
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(256) void k_folded(const CT *__restrict__ P, int Ps
         const int c = cg0 + nt * 16 + li;
         if (o < N && c < C) {
           const int q = c / 3, ch = c - 3 * q;
-          B[((int64_t)q * N + perm[o]) * 3 + ch] = acc[r][nt][v];
+          B[((int64_t)q * N + o) * 3 + ch] = acc[r][nt][v];
         }
       }
     }
@@ -251,8 +262,7 @@ template <int NTN, int MS, int RT>
 __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__restrict__ P, int Psh,
                                                               int K, const float *__restrict__ Lg,
                                                               int Cs, int C, int N,
-                                                              const int32_t *__restrict__ perm,
-                                                              float *__restrict__ B) {
+                                                                            float *__restrict__ B) {
   extern __shared__ __align__(16) unsigned char smem[];
   float *lg = reinterpret_cast<float *>(smem);  // [K * Psh][FOLD_LDW]
   constexpr int G4 = MS / 4, R4 = MS % 4;
@@ -265,7 +275,7 @@ __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__res
   constexpr int G4n = G4 > 0 ? G4 : 1, R4n = R4 > 0 ? R4 : 1;
   // the A operands of term k (issued one term ahead of their matrix work)
   auto load = [&](int k, float4 (&x4)[RT][G4n], float (&x1)[RT][R4n]) {
-    const int64_t koff = (int64_t)k * N * Psh;
+    const int64_t koff = (int64_t)k * Psh;
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
 #pragma unroll
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__res
     for (int r = 0; r < RT; ++r) {
       const int o = ((rb * FOLD_WPB + wave) * RT + r) * 16 + li;
       rok[r] = o < N;
-      prow[r] = P + (int64_t)min(o, N - 1) * Psh;
+      prow[r] = P + (int64_t)min(o, N - 1) * K * Psh;
     }
   };
   rows(blockIdx.x);
@@ -373,7 +383,7 @@ __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__res
           const int c = cg0 + nt * 16 + li;
           if (o < N && c < C) {
             const int q = c / 3, ch = c - 3 * q;
-            B[((int64_t)q * N + perm[o]) * 3 + ch] = acc[r][nt][v];
+            B[((int64_t)q * N + o) * 3 + ch] = acc[r][nt][v];
           }
         }
   }
@@ -383,7 +393,7 @@ size_t folded_lds_bytes(int K, int Psh) { return sizeof(float) * (size_t)K * Psh
 
 template <int NTN, int MS>
 static void folded_lds_rt(dim3 gx, int tiles, hipStream_t st, const float *P, int Psh, int K,
-                          const float *Lg, int Cs, int C, int N, const int32_t *perm, float *B) {
+                          const float *Lg, int Cs, int C, int N, float *B) {
   // Resident workgroups: as many as fit two per compute unit (LDS allowing),
   // split over the column groups; each takes row blocks of FOLD_WPB RT
   // tiles in turn.  RT = 2 unless one tile per wave fills the resident
@@ -400,18 +410,18 @@ static void folded_lds_rt(dim3 gx, int tiles, hipStream_t st, const float *P, in
   const int gxx = std::min((tiles + FOLD_WPB * rt - 1) / (FOLD_WPB * rt), slots);
   if (rt == 2)
     TLT_LAUNCH((k_folded_lds<NTN, MS, 2>), dim3(gxx, gy), dim3(FOLD_WPB * 64), lds, st, P, Psh, K, Lg,
-               Cs, C, N, perm, B);
+               Cs, C, N, B);
   else
     TLT_LAUNCH((k_folded_lds<NTN, MS, 1>), dim3(gxx, gy), dim3(FOLD_WPB * 64), lds, st, P, Psh, K, Lg,
-               Cs, C, N, perm, B);
+               Cs, C, N, B);
 }
 
 template <int NTN>
 static hipError_t folded_lds_ms(dim3 gx, int tiles, hipStream_t st, const float *P, int Psh, int K,
-                                const float *Lg, int Cs, int C, int N, const int32_t *perm, float *B) {
+                                const float *Lg, int Cs, int C, int N, float *B) {
   switch (Psh / 4) {
 #define CASE(m) \
-  case m: folded_lds_rt<NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B); break;
+  case m: folded_lds_rt<NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(7) CASE(8) CASE(9) CASE(12) CASE(16)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -421,25 +431,25 @@ static hipError_t folded_lds_ms(dim3 gx, int tiles, hipStream_t st, const float 
 
 template <typename CT, int NTN, int MS>
 static void folded_rt(dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh, int K, const CT *Lg,
-                      int Cs, int C, int N, const int32_t *perm, CT *B) {
+                      int Cs, int C, int N, CT *B) {
   // tiles per wave: the most that still leaves >= 512 workgroups
   if ((tiles + 15) / 16 >= 512)
     TLT_LAUNCH((k_folded<CT, NTN, MS, 4>), dim3((tiles + 15) / 16, gx.y), dim3(256), 0, st, P, Psh, K,
-               Lg, Cs, C, N, perm, B);
+               Lg, Cs, C, N, B);
   else if ((tiles + 7) / 8 >= 512)
     TLT_LAUNCH((k_folded<CT, NTN, MS, 2>), dim3((tiles + 7) / 8, gx.y), dim3(256), 0, st, P, Psh, K,
-               Lg, Cs, C, N, perm, B);
+               Lg, Cs, C, N, B);
   else
     TLT_LAUNCH((k_folded<CT, NTN, MS, 1>), dim3((tiles + 3) / 4, gx.y), dim3(256), 0, st, P, Psh, K,
-               Lg, Cs, C, N, perm, B);
+               Lg, Cs, C, N, B);
 }
 
 template <typename CT, int NTN>
 static hipError_t folded_ms(dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh, int K,
-                            const CT *Lg, int Cs, int C, int N, const int32_t *perm, CT *B) {
+                            const CT *Lg, int Cs, int C, int N, CT *B) {
   switch (Psh / 4) {
 #define CASE(m) \
-  case m: folded_rt<CT, NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B); break;
+  case m: folded_rt<CT, NTN, m>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(6) CASE(7) CASE(8) CASE(9) CASE(12) CASE(16)
 #undef CASE
     default: return hipErrorInvalidValue;
@@ -449,14 +459,14 @@ static hipError_t folded_ms(dim3 gx, int tiles, hipStream_t st, const CT *P, int
 
 template <typename CT>
 static hipError_t folded_go(int C, int Cs, dim3 gx, int tiles, hipStream_t st, const CT *P, int Psh,
-                            int K, const CT *Lg, int N, const int32_t *perm, CT *B) {
+                            int K, const CT *Lg, int N, CT *B) {
   // real column tiles of the widest group
   const int ntn = (std::min(FOLD_CG, C) + 15) / 16;
   switch (ntn) {
-    case 1: return folded_ms<CT, 1>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
-    case 2: return folded_ms<CT, 2>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
-    case 3: return folded_ms<CT, 3>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
-    default: return folded_ms<CT, 4>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, perm, B);
+    case 1: return folded_ms<CT, 1>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B);
+    case 2: return folded_ms<CT, 2>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B);
+    case 3: return folded_ms<CT, 3>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B);
+    default: return folded_ms<CT, 4>(gx, tiles, st, P, Psh, K, Lg, Cs, C, N, B);
   }
 }
 
@@ -465,7 +475,7 @@ size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64) {
 }
 
 hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
-                         const void *sh, Cols cols, int N, const int32_t *perm, void *B, bool fp64,
+                         const void *sh, Cols cols, int N, void *B, bool fp64,
                          void *scratch, hipStream_t st) {
   if (Psh > 64 || Cs % 16 != 0) return hipErrorInvalidValue;
   const int nw = K * Psh * Cs;
@@ -476,7 +486,7 @@ hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gc
     TLT_LAUNCH(k_fold_weights<double>, dim3((nw + 255) / 256), dim3(256), 0, st,
                (const double *)gcol, Cs, (const double *)sh, cols, K, Psh, n_sh, (double *)scratch);
     e = folded_go<double>(cols.C, Cs, gx, tiles, st, (const double *)P, Psh, K,
-                          (const double *)scratch, N, perm, (double *)B);
+                          (const double *)scratch, N, (double *)B);
   } else {
     TLT_LAUNCH(k_fold_weights<float>, dim3((nw + 255) / 256), dim3(256), 0, st,
                (const float *)gcol, Cs, (const float *)sh, cols, K, Psh, n_sh, (float *)scratch);
@@ -484,14 +494,14 @@ hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gc
       const int ntn = (std::min(FOLD_CG, cols.C) + 15) / 16;
       const float *Pf = (const float *)P, *Lf = (const float *)scratch;
       switch (ntn) {
-        case 1: e = folded_lds_ms<1>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
-        case 2: e = folded_lds_ms<2>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
-        case 3: e = folded_lds_ms<3>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
-        default: e = folded_lds_ms<4>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, perm, (float *)B); break;
+        case 1: e = folded_lds_ms<1>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, (float *)B); break;
+        case 2: e = folded_lds_ms<2>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, (float *)B); break;
+        case 3: e = folded_lds_ms<3>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, (float *)B); break;
+        default: e = folded_lds_ms<4>(gx, tiles, st, Pf, Psh, K, Lf, Cs, cols.C, N, (float *)B); break;
       }
     } else {
       e = folded_go<float>(cols.C, Cs, gx, tiles, st, (const float *)P, Psh, K, (const float *)scratch,
-                           N, perm, (float *)B);
+                           N, (float *)B);
     }
   }
   if (e != hipSuccess) return e;
@@ -499,319 +509,338 @@ hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gc
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint of the transport.
-//
-//   gbar[k][c]  = sum_o dB[c](perm[o]) * V[k][o][c]
-//   X[c][lm]    = sum_o dB[c](perm[o]) * sum_k g[k][c] P[k][o][lm]
-// Per-block partial sums to scratch, then a fixed-order sum over blocks in
-// float64, then thetabar = sum gbar dg and dSH from X.  The float64 path
-// uses one thread per output value and block (ADJ_VB vertices).
+// Adjoint of the transport.  Steps 1-4 of Sec. 4 are linear in the lighting
+// and in the weights g_k, and with the lighting-transfer product
+// P_k = W_k H pad(A o T) (built at load, [N][K][Psh] with vertices in original
+// order) the per-term transport is v_k = P_k L.  Both gradients therefore follow from
+//   Z_k[lm][c] = sum_v P_k[v][lm] dB[q][v][ch]          (c = 3 q + ch)
+//   gbar[k][c] = sum_lm L[light(q)][lm][ch] Z_k[lm][c]   (d loss / d g_k)
+//   X[c][lm]   = sum_k g_k[c] Z_k[lm][c]                 (d loss / d L)
+// P and the upstream gradient dB are each read once, contiguously.  Partial
+// sums of gbar and X per workgroup go to scratch, then a fixed-order float64
+// sum over the partial rows, then thetabar = sum gbar dg/dtheta and dSH
+// from X.
 // ---------------------------------------------------------------------------
 
-constexpr int ADJ_VB = 256;   // vertices per block of the float64 path
-constexpr int ADJ_SPLIT = 16; // first-stage groups of the block reduction
+constexpr int ADJ_VB = 256;   // vertices per partial row of the float64 path
+constexpr int ADJ_SPLIT = 16; // first-stage groups of the row reduction
 
-// Vertices per block of the float32 path: enough blocks to fill the chip.
-static int adj_block_vertices(int N, bool fp64) {
-  if (fp64) return ADJ_VB;
-  int vb = 256;
-  while (vb > 32 && (N + vb - 1) / vb < 1024) vb >>= 1;
-  return vb;
+// float32 path (k_adj_z): one wave per term, eight terms per workgroup,
+// output sets in groups of 16 (48 columns), the upstream gradient staged in
+// LDS in blocks of 64 vertices (column-major, AZ_YS floats per column),
+// vertex ranges split into about AZ_TARGET workgroups (two per compute unit)
+// in steps of 4 vertices.
+constexpr int AZ_VB = 64, AZ_W = 48, AZ_YS = 68, AZ_WAVES = 8, AZ_TARGET = 512, AZ_PD = 8;
+
+struct AdjGeom {
+  int nrow;     // partial rows
+  int nwg;      // vertex ranges
+  int nz;       // term groups (float32 path)
+  int ngroups;  // column groups (float32 path)
+  int span;     // vertices per range
+};
+
+static AdjGeom adj_geom(int N, int K, int C, bool fp64) {
+  AdjGeom g;
+  if (fp64) {
+    g.nwg = (N + ADJ_VB - 1) / ADJ_VB;
+    g.nz = g.ngroups = 1;
+    g.span = ADJ_VB;
+    g.nrow = g.nwg;
+    return g;
+  }
+  g.ngroups = (C + AZ_W - 1) / AZ_W;
+  g.nz = (K + AZ_WAVES - 1) / AZ_WAVES;
+  const int want = std::max(1, AZ_TARGET / (g.ngroups * g.nz));
+  g.span = std::max(4, ((N + want - 1) / want + 3) / 4 * 4);
+  g.nwg = (N + g.span - 1) / g.span;
+  g.nrow = g.nwg * g.nz;
+  return g;
 }
 
-// Scratch layout: per-block partials [nblk][nout] (compute type), the
-// first-stage float64 sums [ADJ_SPLIT][nout], the final float64 sums [nout],
-// and (float32) the Morton-ordered upstream gradient [N][Cs].
+// Scratch layout: partial rows [nrow][nout] (compute type) and the
+// first-stage float64 sums [ADJ_SPLIT][nout].
 struct AdjLayout {
-  size_t part, stage1, red, y, total;
+  size_t part, stage1, total;
 };
 static size_t a256(size_t x) { return (x + 255) / 256 * 256; }
-static AdjLayout adj_layout(int N, int K, int n_sh, int C, int Cs, bool fp64) {
-  const size_t nblk = (N + adj_block_vertices(N, fp64) - 1) / adj_block_vertices(N, fp64);
+static AdjLayout adj_layout(int N, int K, int n_sh, int C, bool fp64) {
+  const AdjGeom g = adj_geom(N, K, C, fp64);
   const size_t nout = (size_t)K * C + (size_t)C * n_sh;
   AdjLayout l;
   l.part = 0;
-  l.stage1 = a256(nblk * nout * (fp64 ? 8 : 4));
-  l.red = l.stage1 + a256((size_t)ADJ_SPLIT * nout * 8);
-  l.y = l.red + a256(nout * 8);
-  l.total = l.y + (fp64 ? 0 : sizeof(float) * (size_t)N * Cs);
+  l.stage1 = a256((size_t)g.nrow * nout * (fp64 ? 8 : 4));
+  l.total = l.stage1 + a256((size_t)ADJ_SPLIT * nout * 8);
   return l;
 }
 
-size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, int Cs, bool fp64) {
-  return adj_layout(N, K, n_sh, C, Cs, fp64).total;
+size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64) {
+  return adj_layout(N, K, n_sh, C, fp64).total;
 }
 
+// float64 path: one thread per output value and partial row (ADJ_VB
+// vertices).
 template <typename CT>
-__global__ __launch_bounds__(256) void k_adj_partial(
-    const CT *__restrict__ dB, const CT *__restrict__ V, int Cs, const CT *__restrict__ P,
-    int Psh, const CT *__restrict__ gcol, const int32_t *__restrict__ perm, int N, int K, int n_sh,
-    int C, CT *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_adj_partial(const CT *__restrict__ dB,
+                                                     const CT *__restrict__ P, int Psh,
+                                                     const CT *__restrict__ gcol, int Cs,
+                                                     const CT *__restrict__ sh, Cols cols, int N,
+                                                     int K, int n_sh, CT *__restrict__ part) {
   const int t = blockIdx.y * 256 + threadIdx.x;
+  const int C = cols.C;
   const int n_g = K * C, n_x = C * n_sh;
   if (t >= n_g + n_x) return;
-  const int o0 = blockIdx.x * ADJ_VB;
-  const int o1 = min(N, o0 + ADJ_VB);
+  const int v0 = blockIdx.x * ADJ_VB;
+  const int v1 = min(N, v0 + ADJ_VB);
   CT acc = 0;
   if (t < n_g) {
     const int k = t / C, c = t - k * C;
     const int q = c / 3, ch = c - 3 * q;
-    for (int o = o0; o < o1; ++o) {
-      const CT d = dB[((int64_t)q * N + perm[o]) * 3 + ch];
-      acc = fma(d, V[((int64_t)k * N + o) * Cs + c], acc);
+    const CT *Lc = sh + (size_t)(cols.n_light > 1 ? q : 0) * n_sh * 3 + ch;
+    for (int v = v0; v < v1; ++v) {
+      const CT *pr = P + ((int64_t)v * K + k) * Psh;
+      CT pl = 0;
+      for (int lm = 0; lm < n_sh; ++lm) pl = fma(pr[lm], Lc[3 * lm], pl);
+      acc = fma(dB[((int64_t)q * N + v) * 3 + ch], pl, acc);
     }
   } else {
     const int u = t - n_g;
     const int c = u / n_sh, lm = u - c * n_sh;
     const int q = c / 3, ch = c - 3 * q;
-    for (int o = o0; o < o1; ++o) {
-      const CT d = dB[((int64_t)q * N + perm[o]) * 3 + ch];
+    for (int v = v0; v < v1; ++v) {
       CT s = 0;
-      for (int k = 0; k < K; ++k) s = fma(gcol[(size_t)k * Cs + c], P[((int64_t)k * N + o) * Psh + lm], s);
-      acc = fma(d, s, acc);
+      for (int k = 0; k < K; ++k) s = fma(gcol[(size_t)k * Cs + c], P[((int64_t)v * K + k) * Psh + lm], s);
+      acc = fma(dB[((int64_t)q * N + v) * 3 + ch], s, acc);
     }
   }
   part[(size_t)blockIdx.x * (n_g + n_x) + t] = acc;
 }
 
-// float32 storage: the same partial sums from three streaming kernels.
-//   k_adj_permute: Y[o][c] = dB[c](perm[o]) in Morton order (stride Cs);
-//   k_adj_gbar:    gbar partials, V and Y streamed as float4 rows (all K
-//                  terms of a vertex block per workgroup, Y rows staged in
-//                  LDS once, when they fit);
-//   k_adj_x:       X partials as a matrix product on the matrix cores over
-//                  the contraction index kappa = (k, o):
-//                  X[c][lm] += sum_kappa (g[k][c] Y[o][c]) * P[k][o][lm],
-//                  v_mfma_f32_16x16x4f32 (exact float32 products, float32
-//                  accumulation).
+// float32 path.  Grid (vertex ranges, column groups, term groups); wave w
+// of term group z owns term k = 8 z + w and accumulates Z_k of its column
+// group over its range on the matrix cores, v_mfma_f32_16x16x4_f32 (exact
+// float32 products, float32 accumulation) with
+//   A[i][kk] = dB at (vertex 4 s + kk, column 16 ct + i)   (staged in LDS)
+//   B[kk][j] = P_k[vertex 4 s + kk][NL j + u]              (from HBM)
+// so tile (ct, u) of lane (j, lg) holds Z_k[NL j + u][16 ct + 4 lg + v] in
+// component v.  Each lane loads NL consecutive P values per step (the 16
+// lanes of a vertex cover a whole P row), through a register ring PD steps
+// ahead of use that runs across the staged blocks.  The gradient block of
+// the next 64 vertices is loaded during the current block's matrix work:
+// lane l of a wave takes vertex l of two output sets (three contiguous
+// channels each, 768 contiguous bytes per wave and set).  In the
+// column-major staging (stride AZ_YS = 68) both the staging stores (64
+// vertices of one column) and the A-operand reads (16 columns x 4 vertices)
+// of a wave fall on 64 distinct banks.
+template <int NCT, int NL>
+__global__ __launch_bounds__(AZ_WAVES * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_z(const float *__restrict__ dB,
+                                                         const float *__restrict__ P, int Psh,
+                                                         const float *__restrict__ gcol, int Cs,
+                                                         const float *__restrict__ sh, Cols cols,
+                                                         int N, int K, int n_sh, int span, int nout,
+                                                         float *__restrict__ part) {
+  __shared__ __align__(16) float ys[2][AZ_W * AZ_YS];   // [column][vertex], vertices >= 64 unused
+  __shared__ float xs[AZ_W * 64];                        // [column][lm]
+  __shared__ float ls[AZ_W * 64];                        // L of the group's columns, [column][lm]
+  __shared__ float gs[AZ_WAVES * AZ_W];                  // g_k of the group's terms and columns
+  constexpr int NTHR = AZ_WAVES * 64;
+  constexpr int GI = AZ_W * AZ_VB / NTHR;                // staged values per thread
+  // the wave index is uniform: read it as such, so the term's buffer
+  // resource and branches are scalar
+  const int t = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int lane = t & 63, li = lane & 15, lg = lane >> 4;
+  const int C = cols.C;
+  const int cg0 = blockIdx.y * AZ_W;
+  const int cw = min(AZ_W, C - cg0);   // real columns of the group (a multiple of 3)
+  const int q0 = cg0 / 3, nq = cw / 3;
+  const int z = blockIdx.z;
+  const int k = z * AZ_WAVES + wave;
+  const bool active = k < K;
+  const int v_begin = blockIdx.x * span;
+  const int v_end = min(N, v_begin + span);
+  const int nv = v_end - v_begin;
+  const int nblk = (nv + AZ_VB - 1) / AZ_VB;
+  const int64_t row = (int64_t)blockIdx.x * gridDim.z + z;
 
-__global__ __launch_bounds__(256) void k_adj_permute(const float *__restrict__ dB,
-                                                     const int32_t *__restrict__ perm, int N, int C,
-                                                     int Cs, float *__restrict__ Y) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)N * Cs) return;
-  const int o = (int)(i / Cs), c = (int)(i - (int64_t)o * Cs);
-  float y = 0.f;
-  if (c < C) {
-    const int q = c / 3, ch = c - 3 * q;
-    y = dB[((int64_t)q * N + perm[o]) * 3 + ch];
-  }
-  Y[i] = y;
-}
-
-// All K terms of a vertex block in one workgroup: the block's Y rows are
-// staged in LDS once (grid nblk; Y read once instead of once per term).
-__global__ __launch_bounds__(256) void k_adj_gbar_all(const float *__restrict__ V,
-                                                      const float *__restrict__ Y, int Cs, int N,
-                                                      int C, int K, int nout, int vb,
-                                                      float *__restrict__ part) {
-  extern __shared__ float4 ys[];     // [vb][Cs/4]
-  __shared__ float4 red[256];
-  const int t = threadIdx.x;
-  const int b = blockIdx.x;
-  const int o0 = b * vb;
-  const int nv = min(vb, N - o0);
-  const int cq = Cs / 4;
-  const int R = 256 / cq;
-  const int q4 = t % cq, r = t / cq;
-  const float4 *y4 = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs);
-  for (int i = t; i < nv * cq; i += 256) ys[i] = y4[i];
-  __syncthreads();
-  for (int k = 0; k < K; ++k) {
-    float4 acc = {0.f, 0.f, 0.f, 0.f};
-    if (r < R) {
-      const float4 *v4 = reinterpret_cast<const float4 *>(V + ((int64_t)k * N + o0) * Cs) + q4;
-#pragma unroll 4
-      for (int ol = r; ol < nv; ol += R) {
-        const float4 v = v4[(int64_t)ol * cq];
-        const float4 y = ys[ol * cq + q4];
-        acc.x = fmaf(v.x, y.x, acc.x);
-        acc.y = fmaf(v.y, y.y, acc.y);
-        acc.z = fmaf(v.z, y.z, acc.z);
-        acc.w = fmaf(v.w, y.w, acc.w);
-      }
-    }
-    red[t] = acc;
-    __syncthreads();
-    if (t < cq) {
-      float4 s = red[t];
-      for (int rr = 1; rr < R; ++rr) {
-        const float4 x = red[rr * cq + t];
-        s.x += x.x;
-        s.y += x.y;
-        s.z += x.z;
-        s.w += x.w;
-      }
-      const float sv[4] = {s.x, s.y, s.z, s.w};
-      for (int u = 0; u < 4; ++u) {
-        const int c = 4 * t + u;
-        if (c < C) part[(size_t)b * nout + (size_t)k * C + c] = sv[u];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// grid (nblk, K): block b, term k.  Thread = (row phase r, column quad).
-__global__ __launch_bounds__(256) void k_adj_gbar(const float *__restrict__ V,
-                                                  const float *__restrict__ Y, int Cs, int N, int C,
-                                                  int nout, int vb, float *__restrict__ part) {
-  __shared__ float4 red[256];
-  const int t = threadIdx.x;
-  const int b = blockIdx.x, k = blockIdx.y;
-  const int o0 = b * vb;
-  const int nv = min(vb, N - o0);
-  const int cq = Cs / 4;            // column quads (Cs is a multiple of 16)
-  const int R = 256 / cq;           // rows in flight per pass
-  const int q4 = t % cq, r = t / cq;
-  float4 acc = {0.f, 0.f, 0.f, 0.f};
-  if (r < R) {
-    const float4 *v4 = reinterpret_cast<const float4 *>(V + ((int64_t)k * N + o0) * Cs) + q4;
-    const float4 *y4 = reinterpret_cast<const float4 *>(Y + (int64_t)o0 * Cs) + q4;
-#pragma unroll 4
-    for (int ol = r; ol < nv; ol += R) {
-      const float4 v = v4[(int64_t)ol * cq];
-      const float4 y = y4[(int64_t)ol * cq];
-      acc.x = fmaf(v.x, y.x, acc.x);
-      acc.y = fmaf(v.y, y.y, acc.y);
-      acc.z = fmaf(v.z, y.z, acc.z);
-      acc.w = fmaf(v.w, y.w, acc.w);
-    }
-  }
-  red[t] = acc;
-  __syncthreads();
-  if (t < cq) {
-    float4 s = red[t];
-    for (int rr = 1; rr < R; ++rr) {
-      const float4 x = red[rr * cq + t];
-      s.x += x.x;
-      s.y += x.y;
-      s.z += x.z;
-      s.w += x.w;
-    }
-    const float sv[4] = {s.x, s.y, s.z, s.w};
-    for (int u = 0; u < 4; ++u) {
-      const int c = 4 * t + u;
-      if (c < C) part[(size_t)b * nout + (size_t)k * C + c] = sv[u];
-    }
-  }
-}
-
-// X partials of block b and column group blockIdx.y (64 columns): every wave
-// takes a quarter of the block's vertices, four at a time, and for each term
-// k multiplies A = (g_k[c] Y[o][c]) by B = P_k[o][lm] into its (c, lm) tiles
-// (MTN x NTN tiles of 16x16 in registers).  Loads carry no branches:
-// addresses are clamped, values past the ends zeroed.  The four waves'
-// tiles are then added in wave order through LDS.
-template <int MTN, int NTN, int KT>
-__global__ __launch_bounds__(256) void k_adj_x(const float *__restrict__ Y, int Cs,
-                                               const float *__restrict__ P, int Psh,
-                                               const float *__restrict__ gcol, int N, int K,
-                                               int n_sh, int C, int nout, int vb,
-                                               float *__restrict__ part) {
-  __shared__ float red[64 * 64];
-  __shared__ float gl[16 * 64];   // K <= 16
-  const int t = threadIdx.x;
-  const int wave = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
-  const int b = blockIdx.x, cg0 = blockIdx.y * 64;
-  const int n_g = K * C;
-  for (int i = t; i < K * 64; i += 256) {
-    const int c = cg0 + (i & 63);
-    gl[i] = c < C ? gcol[(size_t)(i >> 6) * Cs + c] : 0.f;
-  }
-  __syncthreads();
-  const int per = vb / 4;
-  const int ow0 = b * vb + wave * per;
-  const int ow1 = min(ow0 + per, N);
-  f32x4 acc[MTN][NTN];
-#pragma unroll
-  for (int m = 0; m < MTN; ++m)
-#pragma unroll
-    for (int n = 0; n < NTN; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  int ycol[MTN];
-#pragma unroll
-  for (int m = 0; m < MTN; ++m) ycol[m] = min(cg0 + m * 16 + li, Cs - 1);
-  int pcol[NTN];
-  bool pok[NTN];
-#pragma unroll
-  for (int n = 0; n < NTN; ++n) {
-    pok[n] = n * 16 + li < n_sh;
-    pcol[n] = min(n * 16 + li, Psh - 1);
-  }
-  for (int o = ow0; o < ow1; o += 4) {
-    const int orow = o + lk;
-    const bool ook = orow < ow1;
-    const int oc = min(orow, N - 1);
-    float yv[MTN];
-#pragma unroll
-    for (int m = 0; m < MTN; ++m) yv[m] = Y[(int64_t)oc * Cs + ycol[m]];
-    float pv[KT][NTN];   // KT >= K; rows past K repeat row K-1 and are not used
-#pragma unroll
-    for (int k = 0; k < KT; ++k)
-#pragma unroll
-      for (int n = 0; n < NTN; ++n) pv[k][n] = P[((int64_t)min(k, K - 1) * N + oc) * Psh + pcol[n]];
-#pragma unroll
-    for (int m = 0; m < MTN; ++m) yv[m] = ook ? yv[m] : 0.f;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      if (k < K) {
-#pragma unroll
-        for (int m = 0; m < MTN; ++m) {
-          const float a = gl[k * 64 + m * 16 + li] * yv[m];
-#pragma unroll
-          for (int n = 0; n < NTN; ++n)
-            acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, pok[n] ? pv[k][n] : 0.f, acc[m][n], 0, 0, 0);
-        }
-      }
-    }
-  }
-  // the four waves' tiles, added in wave order
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w) {
-#pragma unroll
-      for (int m = 0; m < MTN; ++m)
-#pragma unroll
-        for (int n = 0; n < NTN; ++n)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int idx = (m * 16 + 4 * lk + v) * 64 + n * 16 + li;
-            red[idx] = (w == 0 ? 0.f : red[idx]) + acc[m][n][v];
-          }
-    }
-    __syncthreads();
-  }
-  for (int i = t; i < 64 * 64; i += 256) {
+  // Thread t stages vertex t % 64 of output sets t / 64 and t / 64 + 8 (three
+  // channels each).
+  static_assert(NTHR == 8 * 64 && GI == 6, "staging map: 8 waves x 64 vertices x 2 sets x 3 channels");
+  const int vl_t = t & 63, qa = wave, qb = qa + 8;
+  const bool qa_ok = qa < nq, qb_ok = qb < nq;
+  const float *gsa = dB + ((int64_t)(q0 + (qa_ok ? qa : 0)) * N + v_begin + vl_t) * 3;
+  const float *gsb = dB + ((int64_t)(q0 + (qb_ok ? qb : 0)) * N + v_begin + vl_t) * 3;
+  // L and g_k of the group, for the epilogue, staged once (zeros past the
+  // group's columns and n_sh)
+  for (int i = t; i < AZ_W * 64; i += NTHR) {
     const int cl = i >> 6, lm = i & 63, c = cg0 + cl;
-    if (c < C && lm < n_sh) part[(size_t)b * nout + n_g + (size_t)c * n_sh + lm] = red[i];
+    float x = 0.f;
+    if (cl < cw && lm < n_sh) {
+      const int q = c / 3, ch = c - 3 * q;
+      x = sh[((size_t)(cols.n_light > 1 ? q : 0) * n_sh + lm) * 3 + ch];
+    }
+    ls[i] = x;
+  }
+  for (int i = t; i < AZ_WAVES * AZ_W; i += NTHR) {
+    const int kk = z * AZ_WAVES + i / AZ_W, cl = i % AZ_W;
+    gs[i] = (kk < K && cl < cw) ? gcol[(size_t)kk * Cs + cg0 + cl] : 0.f;
+  }
+
+  float gv[GI];
+  // Branch-free: the loads always run (the vertex clamped into range) and
+  // values outside the range or the group are zeroed only when stored, so no
+  // load sits under a branch and nothing waits on the gather before the
+  // block's matrix work -- the P ring's wait counts stay exact.
+  auto gather = [&](int blk) {
+    const int v = min(v_begin + blk * AZ_VB + vl_t, N - 1);
+    const int64_t off = (int64_t)(v - v_begin - vl_t) * 3;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      gv[ch] = gsa[off + ch];
+      gv[3 + ch] = gsb[off + ch];
+    }
+  };
+  // every (column, vertex) slot of the buffer is written, zeros outside the
+  // range and the group's real columns
+  auto stage = [&](int buf, int blk) {
+    const bool v_ok = v_begin + blk * AZ_VB + vl_t < v_end;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      ys[buf][(3 * qa + ch) * AZ_YS + vl_t] = (qa_ok && v_ok) ? gv[ch] : 0.f;
+      ys[buf][(3 * qb + ch) * AZ_YS + vl_t] = (qb_ok && v_ok) ? gv[3 + ch] : 0.f;
+    }
+  };
+
+  // The range's P rows (all K terms of a vertex are contiguous, so the
+  // workgroup's waves read one stream) through a buffer resource: a step's
+  // lane offset is one 32-bit add, and reads past the range return zeros.
+  const bool lok = NL * li < Psh;
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(P + (int64_t)v_begin * K * Psh), (short)0, nv * K * Psh * (int)sizeof(float),
+      0x00020000);
+  const int step_b = 4 * K * Psh * (int)sizeof(float);
+  const int lane_b = ((lg * K + min(k, K - 1)) * Psh + (lok ? NL * li : 0)) * (int)sizeof(float);
+  auto load_p = [&](int sg, float (&dst)[NL]) {
+    const int off = lane_b + sg * step_b;
+#pragma unroll
+    for (int u = 0; u < NL; ++u)
+      dst[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(prs, off + 4 * u, 0, 0));
+  };
+
+  f32x4 acc[NCT][NL];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+    for (int u = 0; u < NL; ++u) acc[ct][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float ring[AZ_PD][NL];
+#pragma unroll
+  for (int p = 0; p < AZ_PD; ++p) load_p(p, ring[p]);
+
+  gather(0);
+  stage(0, 0);
+  __syncthreads();
+  for (int blk = 0; blk < nblk; ++blk) {
+    const int buf = blk & 1;
+    gather(blk + 1);   // past the last block: clamped, never stored
+    // the gathered values are stored to LDS after this block's matrix work:
+    // keep the scheduler from pulling the stores (and their wait on the
+    // gather, which would drain the P ring) up here
+    __builtin_amdgcn_sched_barrier(0);
+    const int ns = min(AZ_VB / 4, (nv - blk * AZ_VB + 3) / 4);   // steps of this block
+    const float *yb = ys[buf] + li * AZ_YS + lg;
+    // Every block runs all its steps' ring refills (straight-line code, so
+    // the wait counts are the same on every path); steps past the range only
+    // skip their matrix work (their P reads return zeros past the range).
+#pragma unroll
+    for (int g0 = 0; g0 < AZ_VB / 4; g0 += AZ_PD) {
+#pragma unroll
+      for (int p = 0; p < AZ_PD; ++p) {
+        const int s = g0 + p;
+        if (active && s < ns) {
+          float av[NCT];
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) av[ct] = yb[16 * ct * AZ_YS + 4 * s];
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int u = 0; u < NL; ++u)
+              acc[ct][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ct], lok ? ring[p][u] : 0.f,
+                                                                acc[ct][u], 0, 0, 0);
+        }
+        load_p(blk * (AZ_VB / 4) + s + AZ_PD, ring[p]);  // refill PD steps ahead
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (blk + 1 < nblk) stage(buf ^ 1, blk + 1);
+    __syncthreads();
+  }
+
+  // gbar partials of this wave's term: sum over lm within the lane's
+  // column, then over the 16 lanes of a lane group
+  if (active) {
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int cl = 16 * ct + 4 * lg + v, c = cg0 + cl;
+        float sg = 0.f;
+#pragma unroll
+        for (int u = 0; u < NL; ++u) sg = fmaf(ls[cl * 64 + NL * li + u], acc[ct][u][v], sg);
+        sg += __shfl_xor(sg, 1, 64);
+        sg += __shfl_xor(sg, 2, 64);
+        sg += __shfl_xor(sg, 4, 64);
+        sg += __shfl_xor(sg, 8, 64);
+        if (li == 0 && c < cg0 + cw) part[row * nout + (int64_t)k * C + c] = sg;
+      }
+  }
+  // terms of other term groups are zero in this row
+  for (int i = t; i < K * cw; i += NTHR) {
+    const int kk = i / cw, c = cg0 + i % cw;
+    if (kk / AZ_WAVES != z) part[row * nout + (int64_t)kk * C + c] = 0.f;
+  }
+  // X partials: g_k-weighted Z_k of the waves, added in wave order
+  for (int w = 0; w < AZ_WAVES; ++w) {
+    if (wave == w && active) {
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int cl = 16 * ct + 4 * lg + v;
+          const float gk = gs[wave * AZ_W + cl];
+#pragma unroll
+          for (int u = 0; u < NL; ++u) {
+            const int idx = cl * 64 + NL * li + u;
+            xs[idx] = (w == 0 ? 0.f : xs[idx]) + gk * acc[ct][u][v];
+          }
+        }
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < cw * n_sh; i += NTHR) {
+    const int cl = i / n_sh, lm = i - cl * n_sh;
+    part[row * nout + (int64_t)K * C + (int64_t)(cg0 + cl) * n_sh + lm] = xs[cl * 64 + lm];
   }
 }
 
-template <int MTN, int KT>
-static void adj_x_go(int ntn, dim3 g, hipStream_t st, const float *Y, int Cs, const float *P, int Psh,
-                     const float *gcol, int N, int K, int n_sh, int C, int nout, int vb, float *part) {
-  switch (ntn) {
-#define ADJX(n)                                                                                 \
-  case n:                                                                                       \
-    TLT_LAUNCH((k_adj_x<MTN, n, KT>), g, dim3(256), 0, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, \
-               nout, vb, part);                                                                 \
-    break;
-    ADJX(1) ADJX(2) ADJX(3) ADJX(4)
-#undef ADJX
+template <int NCT>
+static hipError_t adj_z_nl(int nl, dim3 g, hipStream_t st, const float *dB, const float *P, int Psh,
+                           const float *gcol, int Cs, const float *sh, Cols cols, int N, int K,
+                           int n_sh, int span, int nout, float *part) {
+  switch (nl) {
+#define AZ(n)                                                                                      \
+  case n:                                                                                          \
+    TLT_LAUNCH((k_adj_z<NCT, n>), g, dim3(AZ_WAVES * 64), 0, st, dB, P, Psh, gcol, Cs, sh, cols, N, \
+               K, n_sh, span, nout, part);                                                         \
+    return hipSuccess;
+    AZ(1) AZ(2) AZ(3) AZ(4)
+#undef AZ
   }
+  return hipErrorInvalidValue;
 }
 
-template <int MTN>
-static void adj_x_k(int ntn, dim3 g, hipStream_t st, const float *Y, int Cs, const float *P, int Psh,
-                    const float *gcol, int N, int K, int n_sh, int C, int nout, int vb, float *part) {
-  if (K <= 4) adj_x_go<MTN, 4>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
-  else if (K <= 8) adj_x_go<MTN, 8>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
-  else adj_x_go<MTN, 16>(ntn, g, st, Y, Cs, P, Psh, gcol, N, K, n_sh, C, nout, vb, part);
-}
-
-// Sum of the per-block partials in a fixed order, in float64.  Stage 1:
-// grid (output chunks of 64, ADJ_SPLIT groups of blocks); lane = output,
-// wave w sums a contiguous quarter of the group's blocks, the quarters are
-// added in order.  Stage 2: the ADJ_SPLIT group sums, in order.
+// Sum of the partial rows in a fixed order, in float64.  Stage 1: grid
+// (output chunks of 64, ADJ_SPLIT groups of rows); lane = output, wave w sums
+// a contiguous quarter of the group's rows, the quarters are added in order.
+// Stage 2 (in k_adj_final): the ADJ_SPLIT group sums, in order.
 template <typename CT>
 __global__ __launch_bounds__(256) void k_adj_reduce(const CT *__restrict__ part, int nblk, int nout,
                                                     double *__restrict__ stage1) {
@@ -832,108 +861,86 @@ __global__ __launch_bounds__(256) void k_adj_reduce(const CT *__restrict__ part,
     stage1[(size_t)g * nout + t] = ((q4[0][lane] + q4[1][lane]) + q4[2][lane]) + q4[3][lane];
 }
 
-__global__ __launch_bounds__(256) void k_adj_reduce2(const double *__restrict__ stage1, int nout,
-                                                     double *__restrict__ out) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= nout) return;
-  double s = 0.0;
-  for (int g = 0; g < ADJ_SPLIT; ++g) s += stage1[(size_t)g * nout + t];
-  out[t] = s;
-}
-
-// thetabar[m][ch][p] and dSH[l][lm][ch] from the reduced sums.
+// thetabar[m][ch][p] and dSH[l][lm][ch] straight from the ADJ_SPLIT group
+// sums: every reduced value is the sum of its groups in order (as a second
+// reduction pass would form it), taken where it is used.
 template <typename CT>
-__global__ void k_adj_out(const double *__restrict__ red, const double *__restrict__ dg64, int K,
-                          int n_sh, Cols cols, CT *__restrict__ dSH, double *__restrict__ dTheta) {
-  const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_adj_final(const double *__restrict__ stage1, int nout,
+                                                   const double *__restrict__ dg64, int K, int n_sh,
+                                                   Cols cols, CT *__restrict__ dSH,
+                                                   double *__restrict__ dTheta) {
+  const int gt = blockIdx.x * 256 + threadIdx.x;
   const int C = cols.C;
-  const double *gbar = red;             // [K][C]
-  const double *X = red + (size_t)K * C; // [C][n_sh]
   const int n_th = cols.n_mat * 9;
-  const int n_l = cols.n_light * n_sh * 3;
+  auto red = [&](size_t i) {
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < ADJ_SPLIT; ++g) s += stage1[(size_t)g * nout + i];
+    return s;
+  };
   if (gt < n_th * 64) {
-    // one wave per material derivative: lanes take (output set, term)
-    // pairs with independent loads, then a fixed-order wave sum
-    const int t = gt >> 6, lane = gt & 63;
-    const int m = t / 9, ch = (t / 3) % 3, p = t % 3;
+    // one wave per material derivative: lanes take (output set, term) pairs
+    // with independent loads, then a fixed-order wave sum
+    const int d = gt >> 6, lane = gt & 63;
+    const int m = d / 9, ch = (d / 3) % 3, p = d % 3;
     double s = 0.0;
     for (int i = lane; i < cols.n_out * K; i += 64) {
       const int q = i / K, k = i - q * K;
       const int mq = cols.n_mat > 1 ? q : 0;
-      if (mq == m) s += gbar[(size_t)k * C + 3 * q + ch] * dg64[(((size_t)m * 3 + ch) * K + k) * 3 + p];
+      if (mq == m) s += red((size_t)k * C + 3 * q + ch) * dg64[(((size_t)m * 3 + ch) * K + k) * 3 + p];
     }
     s = wave_sum(s);
-    if (lane == 0) dTheta[t] = s;
-  } else if (gt < n_th * 64 + n_l) {
+    if (lane == 0) dTheta[d] = s;
+  } else if (gt < n_th * 64 + cols.n_light * n_sh * 3) {
     const int u = gt - n_th * 64;
     const int l = u / (n_sh * 3), lm = (u / 3) % n_sh, ch = u % 3;
     double s = 0.0;
     for (int q = 0; q < cols.n_out; ++q) {
       const int lq = cols.n_light > 1 ? q : 0;
-      if (lq != l) continue;
-      s += X[(size_t)(3 * q + ch) * n_sh + lm];
+      if (lq == l) s += red((size_t)K * C + (size_t)(3 * q + ch) * n_sh + lm);
     }
     dSH[u] = (CT)s;
   }
 }
 
-hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, int Psh,
-                          const void *gcol, const double *dg64, const int32_t *perm, int N, int K,
-                          int n_sh, Cols cols, bool fp64, void *partial, size_t partial_bytes,
-                          void *dSH, double *dTheta, hipStream_t st) {
+hipError_t launch_adjoint(const void *dB, const void *P, int Psh, const void *gcol, int Cs,
+                          const void *sh, const double *dg64, int N, int K, int n_sh, Cols cols,
+                          bool fp64, void *partial, size_t partial_bytes, void *dSH, double *dTheta,
+                          hipStream_t st) {
   const int C = cols.C;
-  const int vb = adj_block_vertices(N, fp64);
-  const int nblk = (N + vb - 1) / vb;
   const int nout = K * C + C * n_sh;
-  const AdjLayout l = adj_layout(N, K, n_sh, C, Cs, fp64);
+  const AdjGeom geo = adj_geom(N, K, C, fp64);
+  const AdjLayout l = adj_layout(N, K, n_sh, C, fp64);
   if (partial_bytes < l.total) return hipErrorInvalidValue;
   double *stage1 = (double *)((char *)partial + l.stage1);
-  double *red = (double *)((char *)partial + l.red);
-  const int n_fin = cols.n_mat * 9 * 64 + cols.n_light * n_sh * 3;  // a wave per material derivative
   const dim3 gr((nout + 63) / 64, ADJ_SPLIT);
   if (fp64) {
-    const dim3 g1(nblk, (nout + 255) / 256);
-    TLT_LAUNCH(k_adj_partial<double>, g1, dim3(256), 0, st, (const double *)dB,
-                       (const double *)V, Cs, (const double *)P, Psh, (const double *)gcol, perm,
-                       N, K, n_sh, C, (double *)partial);
-    TLT_LAUNCH(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, nblk,
-                       nout, stage1);
+    const dim3 g1(geo.nwg, (nout + 255) / 256);
+    TLT_LAUNCH(k_adj_partial<double>, g1, dim3(256), 0, st, (const double *)dB, (const double *)P, Psh,
+               (const double *)gcol, Cs, (const double *)sh, cols, N, K, n_sh, (double *)partial);
+    TLT_LAUNCH(k_adj_reduce<double>, gr, dim3(256), 0, st, (const double *)partial, geo.nrow, nout,
+               stage1);
   } else {
-    if (Cs % 16 != 0 || Cs > 1024 || Psh > 64 || K > 16 || n_sh > 64) return hipErrorInvalidValue;
-    float *Y = (float *)((char *)partial + l.y);
-    const int64_t ny = (int64_t)N * Cs;
-    // (a vertex-major form with scattered row writes measured 2.6x slower)
-    TLT_LAUNCH(k_adj_permute, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st,
-               (const float *)dB, perm, N, C, Cs, Y);
-    // one workgroup per block for all terms when there are enough blocks to
-    // fill the chip and the block's Y rows fit the LDS budget
-    const size_t ylds = sizeof(float) * (size_t)vb * Cs;
-    if (ylds <= 64 * 1024 && nblk >= 1024)
-      TLT_LAUNCH(k_adj_gbar_all, dim3(nblk), dim3(256), ylds, st, (const float *)V, Y, Cs, N, C, K,
-                 nout, vb, (float *)partial);
-    else
-      TLT_LAUNCH(k_adj_gbar, dim3(nblk, K), dim3(256), 0, st, (const float *)V, Y, Cs, N, C,
-                 nout, vb, (float *)partial);
-    {
-      const dim3 gx(nblk, (C + 63) / 64);
-      const int mtn = (std::min(64, C) + 15) / 16, ntn = (n_sh + 15) / 16;
-      const float *Pf = (const float *)P, *gf = (const float *)gcol;
-      float *pf = (float *)partial;
-      if (mtn == 1) adj_x_k<1>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
-      else if (mtn == 2) adj_x_k<2>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
-      else if (mtn == 3) adj_x_k<3>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
-      else adj_x_k<4>(ntn, gx, st, Y, Cs, Pf, Psh, gf, N, K, n_sh, C, nout, vb, pf);
-    }
-    TLT_LAUNCH(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, nblk,
-                       nout, stage1);
+    if (Psh > 64 || n_sh > Psh || Psh % ((Psh + 15) / 16) != 0) return hipErrorInvalidValue;
+    const dim3 gz(geo.nwg, geo.ngroups, geo.nz);
+    const int nct = (std::min(AZ_W, C) + 15) / 16, nl = (Psh + 15) / 16;
+    const float *dBf = (const float *)dB, *Pf = (const float *)P, *gf = (const float *)gcol;
+    const float *shf = (const float *)sh;
+    float *pf = (float *)partial;
+    hipError_t e;
+    if (nct == 1) e = adj_z_nl<1>(nl, gz, st, dBf, Pf, Psh, gf, Cs, shf, cols, N, K, n_sh, geo.span, nout, pf);
+    else if (nct == 2) e = adj_z_nl<2>(nl, gz, st, dBf, Pf, Psh, gf, Cs, shf, cols, N, K, n_sh, geo.span, nout, pf);
+    else e = adj_z_nl<3>(nl, gz, st, dBf, Pf, Psh, gf, Cs, shf, cols, N, K, n_sh, geo.span, nout, pf);
+    if (e != hipSuccess) return e;
+    TLT_LAUNCH(k_adj_reduce<float>, gr, dim3(256), 0, st, (const float *)partial, geo.nrow, nout, stage1);
   }
-  TLT_LAUNCH(k_adj_reduce2, dim3((nout + 255) / 256), dim3(256), 0, st, stage1, nout, red);
+  const int n_fin = cols.n_mat * 9 * 64 + cols.n_light * n_sh * 3;  // a wave per material derivative
   if (fp64)
-    TLT_LAUNCH(k_adj_out<double>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
-                       K, n_sh, cols, (double *)dSH, dTheta);
+    TLT_LAUNCH(k_adj_final<double>, dim3((n_fin + 255) / 256), dim3(256), 0, st, stage1, nout, dg64, K,
+               n_sh, cols, (double *)dSH, dTheta);
   else
-    TLT_LAUNCH(k_adj_out<float>, dim3((n_fin + 255) / 256), dim3(256), 0, st, red, dg64,
-                       K, n_sh, cols, (float *)dSH, dTheta);
+    TLT_LAUNCH(k_adj_final<float>, dim3((n_fin + 255) / 256), dim3(256), 0, st, stage1, nout, dg64, K,
+               n_sh, cols, (float *)dSH, dTheta);
   return hipGetLastError();
 }
 

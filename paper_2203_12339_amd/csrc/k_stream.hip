@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_stream(StreamArgs a) {
           const CT t = wave_sum(acc[c]);
           if (lane == c) mine = t;
         }
-        if (lane < CPL) vsave[((int64_t)k * a.N + o) * a.vs_stride + c0 + lane] = mine;
+        if (lane < CPL) vsave[((int64_t)a.perm[o] * K + k) * a.vs_stride + c0 + lane] = mine;
       }
 #pragma unroll
       for (int c = 0; c < CPL; ++c) acc[c] = 0;

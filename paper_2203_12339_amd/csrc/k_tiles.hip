@@ -326,7 +326,8 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     ns = ns_next;
   }
 
-  // ---- epilogue: v_k (optional) and the K-term fusion into B ----
+  // ---- epilogue: v_k (optional; row (perm[o], k), vertex-major in original
+  // vertex order) and the K-term fusion into B ----
   const int K = a.K;
   const int lg = lane >> 4, ln = lane & 15;
   const float *gcol = (const float *)a.gcol;
@@ -342,7 +343,8 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
         for (int v = 0; v < 4; ++v) {
           const int row = (wm * MTW + m) * 16 + 4 * lg + v;
           const int o = b * a.V + row / K, k = row % K;
-          if (c < a.C && o < a.N) vsave[((int64_t)k * a.N + o) * a.vs_stride + c] = acc[m][nt][v];
+          if (c < a.C && o < a.N)
+            vsave[((int64_t)a.perm[o] * K + k) * a.vs_stride + c] = acc[m][nt][v];
         }
       }
   }

@@ -86,7 +86,7 @@ struct StreamArgs {
   const void *gcol;        // [K][Cs]
   const int32_t *perm;     // [N]
   void *B;                 // [n_out][N][3] or nullptr
-  void *vsave;             // [K][N][vs_stride] or nullptr
+  void *vsave;             // [N][K][vs_stride] or nullptr; row (perm[o], k)
   int vs_stride;
   int64_t R;               // N*K rows
   int n_waves;             // <= N
@@ -110,7 +110,7 @@ struct TileArgs {
   const void *gcol;        // [K][Cs] float32, or nullptr with B == nullptr
   const int32_t *perm;
   void *B;                 // [n_out][N][3] float32 or nullptr
-  void *vsave;             // [K][N][vs_stride] or nullptr
+  void *vsave;             // [N][K][vs_stride] or nullptr; row (perm[o], k)
   int vs_stride;
   int max_union;           // largest union of a block (entries)
   int shape;               // 16-bit kinds, 8 m-tiles: 100 MTW + 10 NT + IPT, 0 = built-in
@@ -127,22 +127,25 @@ constexpr size_t TILE_VAL_SLACK = 128 * 1024;
 hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols, int N,
                        const int32_t *perm, bool fp64, hipStream_t st);
 
-// Material-only update: B from saved v_k [K][N][Cs] and gcol.
-hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C,
-                          const int32_t *perm, void *B, bool fp64, hipStream_t st);
+// Material-only update: B from kept v_k [N][K][Cs] (vertices in original
+// order) and gcol.
+hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N, int C, void *B,
+                          bool fp64, hipStream_t st);
 
-// Folded lighting transport: B = sum_k g_k P_k L (P_k = W_k H (A o T)).
+// Folded lighting transport: B = sum_k g_k P_k L (P_k = W_k H (A o T), stored
+// [N][K][Psh], vertices in original order).
 hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
-                         const void *sh, Cols cols, int N, const int32_t *perm, void *B, bool fp64,
-                         void *scratch, hipStream_t st);
+                         const void *sh, Cols cols, int N, void *B, bool fp64, void *scratch,
+                         hipStream_t st);
 size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64);
 
-// Adjoint: partial sums over vertex blocks, then the final reduction.
-hipError_t launch_adjoint(const void *dB, const void *V, int Cs, const void *P, int Psh,
-                          const void *gcol, const double *dg64, const int32_t *perm, int N, int K,
-                          int n_sh, Cols cols, bool fp64, void *partial, size_t partial_bytes,
-                          void *dSH, double *dTheta, hipStream_t st);
-size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, int Cs, bool fp64);
+// Adjoint from Z_k = P_k^T dB: partial rows, then the final reduction.
+// `partial` holds adjoint_partial_bytes(N, K, n_sh, C, fp64) bytes.
+hipError_t launch_adjoint(const void *dB, const void *P, int Psh, const void *gcol, int Cs,
+                          const void *sh, const double *dg64, int N, int K, int n_sh, Cols cols,
+                          bool fp64, void *partial, size_t partial_bytes, void *dSH, double *dTheta,
+                          hipStream_t st);
+size_t adjoint_partial_bytes(int N, int K, int n_sh, int C, bool fp64);
 
 // Load-time transport build on the device: kernel rows, Haar transform and
 // exact top-n selection for vertices [o0, o0 + nv) and the k of one group.

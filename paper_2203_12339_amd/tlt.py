@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libtlt.so")
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
 WAVELET_NONE, WAVELET_HAAR = 0, 1
-SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS, FOLDED_LIGHTING, SPATIAL = 1, 2, 4, 8, 16
+SAVE_FOR_BACKWARD, FORCE_FULL, PLAIN_ROWS, FOLDED_LIGHTING, SPATIAL, KEEP_TERMS = 1, 2, 4, 8, 16, 32
 LAYOUTS = {"auto": 0, "rows": 1, "tiles": 2}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 
@@ -482,7 +482,11 @@ class Renderer:
         import torch
         return torch.float64 if self.fp64 else torch.float32
 
-    def render(self, out=None, save=False, force=False, plain=False, folded=False, spatial=False):
+    def render(self, out=None, save=False, force=False, plain=False, folded=False, spatial=False,
+               keep=False):
+        """save: render_backward may differentiate this render; keep: keep the
+        per-term transport v_k so that a material-only change reruns Steps 3-4
+        only (render flags TLT_SAVE_FOR_BACKWARD, TLT_KEEP_TERMS)."""
         import torch
         if out is None:
             out = torch.empty((self.n_out, self.N, 3), dtype=self.out_dtype(),
@@ -492,7 +496,7 @@ class Renderer:
             assert tuple(out.shape) == (self.n_out, self.N, 3), tuple(out.shape)
         flags = (SAVE_FOR_BACKWARD if save else 0) | (FORCE_FULL if force else 0) | \
             (PLAIN_ROWS if plain else 0) | (FOLDED_LIGHTING if folded else 0) | \
-            (SPATIAL if spatial else 0)
+            (SPATIAL if spatial else 0) | (KEEP_TERMS if keep else 0)
         self.render_status = _check(_render(self._h, ctypes.c_void_p(out.data_ptr()), _stream(), flags),
                                     self._h, allow=(OK, W_BF16_NO_RESIDUAL))
         self.generation += 1
