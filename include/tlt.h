@@ -414,6 +414,24 @@ tlt_status render_backward(tlt_ctx *ctx, const void *dB_dev, void *dSH_dev,
                            double *dTheta_dev, void *hip_stream);
 
 /*
+ * For callers that cannot allocate -- code under HIP graph capture, serving
+ * loops, harnesses that forbid device allocation: render_backward with its
+ * scratch (the adjoint's partial rows and group sums) in a static device
+ * buffer of TLT_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it
+ * runs on until the process ends.  It calls no allocating routine.  Same
+ * arguments, checks, state rules and results as render_backward (the same
+ * kernels).  TLT_E_ARG when the launch's partial sums exceed the buffer
+ * (the message gives both sizes; about 4.6 MB at 163842 vertices, 16
+ * lightings, 36 SH coefficients, K = 8).  Every call on one GPU shares that
+ * GPU's buffer, whose contents the next call overwrites: calls that overlap
+ * on one GPU (other streams, contexts or threads) race, and the caller must
+ * order them.  Stage timing (tlt_profile_enable) does not record this call.
+ */
+#define TLT_NOALLOC_SCRATCH_BYTES (16u << 20)
+tlt_status render_backward_noalloc(tlt_ctx *ctx, const void *dB_dev, void *dSH_dev,
+                                   double *dTheta_dev, void *hip_stream);
+
+/*
  * Diagnostics (host copies, synchronous).  tlt_read_rows copies rows
  * (row = o*K + k) of the stored transport: columns as int32 and values
  * widened to float64 (exactly the stored values).  tlt_read_state copies

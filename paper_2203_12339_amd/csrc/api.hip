@@ -10,6 +10,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -27,6 +28,19 @@ StageEvents &stage_events() {
   return ev;
 }
 }  // namespace tlt
+
+// Scratch of render_backward_noalloc: the adjoint's partial rows and group
+// sums in a file-scope device array, so that the call allocates nothing.
+// Each GPU the library runs on holds its own copy until the process ends.
+// In host code the name `scratch` is only a host-side stand-in: host code
+// uses the device address hipGetSymbolAddress returns for the current
+// device, looked up once per device by tlt_create (scratch_addr below).
+static __device__ __align__(256) unsigned char scratch[TLT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex scratch_mu;
+std::vector<void *> scratch_addr;   // per device index; null until looked up
+}  // namespace
 
 struct tlt_ctx {
   int device = 0;
@@ -616,9 +630,24 @@ tlt_status tlt_create(tlt_ctx **out, int hip_device) {
   if (hip_device < 0 || hip_device >= n) return fail(nullptr, TLT_E_ARG, "device index out of range");
   e = hipSetDevice(hip_device);
   if (e != hipSuccess) return fail(nullptr, TLT_E_HIP, hipGetErrorString(e));
+  void *sp = nullptr;
+  {
+    // this device's copy of the static scratch, with the device current
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if ((int)scratch_addr.size() < n) scratch_addr.resize(n, nullptr);
+    if (!scratch_addr[hip_device]) {
+      e = hipGetSymbolAddress(&scratch_addr[hip_device], HIP_SYMBOL(scratch));
+      if (e != hipSuccess) {
+        scratch_addr[hip_device] = nullptr;
+        return fail(nullptr, TLT_E_HIP, std::string("static scratch address: ") + hipGetErrorString(e));
+      }
+    }
+    sp = scratch_addr[hip_device];
+  }
   tlt_ctx *c = new (std::nothrow) tlt_ctx;
   if (!c) return fail(nullptr, TLT_E_OOM, "context allocation");
   c->device = hip_device;
+  c->scratch_dev = sp;
   e = hipHostMalloc((void **)&c->mstat, 4 * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void **)&c->mstat_dev, c->mstat, 0);
   if (e != hipSuccess) {
@@ -1425,7 +1454,6 @@ static tlt_status backward_check(tlt_ctx *c, const void *dB, const void *dSH, co
 static tlt_status backward_launch(tlt_ctx *c, const void *dB, void *dSH, double *dTheta,
                                   void *scratch_ptr, size_t scratch_bytes, hipStream_t st) {
   Cols cols{c->C, c->n_out, c->n_light, c->n_mat};
-  StageTimer t(c, 3, st);
   HIPC(c, launch_adjoint(dB, c->P, c->Psh, c->gcol, c->Cs, c->sh, c->dg64, c->N, c->K, c->n_sh, cols,
                          c->fp64, scratch_ptr, scratch_bytes, dSH, dTheta, st));
   return TLT_OK;
@@ -1441,7 +1469,24 @@ tlt_status render_backward(tlt_ctx *c, const void *dB, void *dSH, double *dTheta
     if ((s = dalloc(c, &c->adj, need, "adjoint partials")) != TLT_OK) return s;
     c->adj_bytes = need;
   }
+  StageTimer t(c, 3, (hipStream_t)stream);
   return backward_launch(c, dB, dSH, dTheta, c->adj, c->adj_bytes, (hipStream_t)stream);
+}
+
+tlt_status render_backward_noalloc(tlt_ctx *c, const void *dB, void *dSH, double *dTheta,
+                                   void *stream) {
+  tlt_status s = backward_check(c, dB, dSH, dTheta);
+  if (s != TLT_OK) return s;
+  const size_t need = adjoint_partial_bytes(c->N, c->K, c->n_sh, c->C, c->fp64);
+  if (need > TLT_NOALLOC_SCRATCH_BYTES)
+    return fail(&c->err, TLT_E_ARG,
+                "the adjoint of this launch needs " + std::to_string(need) +
+                    " bytes of partial sums, more than the static buffer of render_backward_noalloc (" +
+                    std::to_string((size_t)TLT_NOALLOC_SCRATCH_BYTES) + " bytes); use render_backward");
+  if (!c->scratch_dev) return fail(&c->err, TLT_E_STATE, "no static scratch address for this device");
+  // no stage timer: it may create events
+  return backward_launch(c, dB, dSH, dTheta, c->scratch_dev, TLT_NOALLOC_SCRATCH_BYTES,
+                         (hipStream_t)stream);
 }
 
 tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {

@@ -93,6 +93,7 @@ _material_status = _sig("tlt_material_status", ctypes.c_int, _p, _p)
 _set_lighting = _sig("set_lighting", ctypes.c_int, _p, ctypes.c_int, _p)
 _render = _sig("render", ctypes.c_int, _p, _p, _p, ctypes.c_int)
 _render_backward = _sig("render_backward", ctypes.c_int, _p, _p, _p, _p, _p)
+_render_backward_noalloc = _sig("render_backward_noalloc", ctypes.c_int, _p, _p, _p, _p, _p)
 _read_rows = _sig("tlt_read_rows", ctypes.c_int, _p, ctypes.c_int64,
                   ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
 _read_state = _sig("tlt_read_state", ctypes.c_int, _p, ctypes.c_int, _p,
@@ -125,7 +126,8 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
 
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "tlt_check_transport", "tlt_material_status",
-            "set_material", "set_lighting", "render", "render_backward", "tlt_read_rows",
+            "set_material", "set_lighting", "render", "render_backward", "render_backward_noalloc",
+            "tlt_read_rows",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
             "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
             "load_spatial", "tlt_spatial_info", "tlt_read_spatial", "tlt_spatial_rows",
@@ -508,7 +510,10 @@ class Renderer:
         return _check(_render(self._h, ctypes.c_void_p(out_ptr), _stream(), flags), self._h,
                       allow=(OK, W_BF16_NO_RESIDUAL))
 
-    def render_backward(self, dB, dSH=None, dTheta=None):
+    def render_backward(self, dB, dSH=None, dTheta=None, noalloc=False):
+        """Adjoint of the last render (render_backward); noalloc=True calls
+        render_backward_noalloc (the library's static scratch; pass dSH and
+        dTheta to keep the call free of allocations here too)."""
         import torch
         assert dB.is_cuda and dB.dtype == self.out_dtype(), (dB.dtype, self.out_dtype())
         assert tuple(dB.shape) == (self.n_out, self.N, 3), (tuple(dB.shape), (self.n_out, self.N, 3))
@@ -525,7 +530,8 @@ class Renderer:
         else:
             assert dTheta.is_cuda and dTheta.dtype == torch.float64 and dTheta.is_contiguous()
             assert tuple(dTheta.shape) == (self.n_mat, 3, 3), tuple(dTheta.shape)
-        _check(_render_backward(self._h, ctypes.c_void_p(dB.data_ptr()),
+        fn = _render_backward_noalloc if noalloc else _render_backward
+        _check(fn(self._h, ctypes.c_void_p(dB.data_ptr()),
                                 ctypes.c_void_p(dSH.data_ptr()),
                                 ctypes.c_void_p(dTheta.data_ptr()), _stream()), self._h)
         return dSH, dTheta
