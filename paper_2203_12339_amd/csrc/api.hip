@@ -428,6 +428,7 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   a.vs_stride = vs_stride;
   a.kc = c->tune_tile_chunk;
   a.shape = c->tune_tile_shape;
+  a.stream_w = c->t_val_bytes > ((size_t)256 << 20);   // MI355X Infinity Cache: 256 MB
   return a;
 }
 

@@ -42,8 +42,9 @@ template <> struct TileKind<0> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static constexpr int VSZ = 4;  // bytes per stored value
+  template <int AUX>
   static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) { hi = x; lo = 0; }
 };
@@ -56,8 +57,9 @@ template <> struct TileKind<1> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
   static constexpr int VSZ = 2;
+  template <int AUX>
   static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) {
     hi = (__bf16)x;
@@ -73,8 +75,9 @@ template <> struct TileKind<2> {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
   static constexpr int VSZ = 2;
+  template <int AUX>
   static __device__ __forceinline__ AFrag frag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    return __builtin_bit_cast(AFrag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX));
   }
   static __device__ __forceinline__ void split(float x, BElem &hi, BElem &lo) {
     hi = (_Float16)x;
@@ -99,7 +102,15 @@ constexpr int TILE_LDS = 64 * 1024;  // staging budget per workgroup
 // CSC: k-steps per staged chunk, a compile-time multiple of PD, so the
 // matrix work of a chunk is straight-line code and the load counters can
 // be waited on exactly.
-template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC>
+// WAUX: cache policy of the W loads -- 2 (non-temporal) when the tile
+// values exceed the Infinity Cache and a block is read by one column group
+// only (W then streams past the caches, which keep the gathered irradiance
+// rows: measured 2062 -> 1936 us at 163842 vertices, 48 columns), else 0:
+// several column groups re-read a block through L2 (non-temporal measured
+// 624 -> 694 us at 40962 vertices, 192 columns in three groups), and tiles
+// that fit the Infinity Cache stay there from one render to the next
+// (non-temporal measured 41.8 -> 44.7 us at 10242 vertices, 232 MB).
+template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC, int WAUX>
 __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   typedef TileKind<KIND> TK;
   typedef typename TK::BElem BElem;
@@ -237,7 +248,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   for (int m = 0; m < MTW; ++m) loff[m] = ((wm * MTW + m) * 64 + lane) * KPL * TK::VSZ;
   auto load_a = [&](int s, AFrag (&dst)[MTW]) {
 #pragma unroll
-    for (int m = 0; m < MTW; ++m) dst[m] = TK::frag(wrs, loff[m], s * step_bytes);
+    for (int m = 0; m < MTW; ++m) dst[m] = TK::template frag<WAUX>(wrs, loff[m], s * step_bytes);
   };
   // B fragments of step sl of the staged chunk (unconditional LDS reads).
   // 16-bit kinds: the fragment of (step, column tile nt, half h) holds lane
@@ -421,7 +432,10 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   const size_t step_bytes = (size_t)(a.R / 16) * 64 * TileKind<KIND>::KPL * TileKind<KIND>::VSZ;
   if ((size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
-  TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC>), dim3(hw), dim3(threads), lds, st, a);
+  if (a.n_groups == 1 && a.stream_w)
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2>), dim3(hw), dim3(threads), lds, st, a);
+  else
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0>), dim3(hw), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 

@@ -114,6 +114,7 @@ struct TileArgs {
   int vs_stride;
   int max_union;           // largest union of a block (entries)
   int shape;               // 16-bit kinds, 8 m-tiles: 100 MTW + 10 NT + IPT, 0 = built-in
+  int stream_w;            // 1: the tile values exceed the Infinity Cache (W streams once)
   int wn, kc, n_groups, uc_offset;  // set by launch_tiles
 };
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
