@@ -168,6 +168,22 @@ def test_icosahedron_areas_golden():
     np.testing.assert_allclose(geometry.vertex_normals(V, F), V, atol=1e-14)
 
 
+def test_vertex_normals_weight_faces_by_area():
+    """Reading 10 on a vertex where the weighting shows: vertex 0 lies on a
+    face of area 1/2 with normal +z and a face of area 3/2 with normal +x,
+    so its area-weighted normal is (3, 0, 1)/sqrt(10) (a plain average of
+    the face normals would give (1, 0, 1)/sqrt(2)), and its area is
+    (1/2 + 3/2)/3.  Worked by hand."""
+    V = np.array([[0.0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 3, 0], [0, 0, 1]])
+    F = np.array([[0, 1, 2], [0, 3, 4]])
+    n = geometry.vertex_normals(V, F)
+    np.testing.assert_allclose(n[0], np.array([3.0, 0.0, 1.0]) / np.sqrt(10.0), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(n[1], [0.0, 0.0, 1.0], atol=1e-15)
+    np.testing.assert_allclose(n[3], [1.0, 0.0, 0.0], atol=1e-15)
+    A = geometry.vertex_areas(V, F)
+    np.testing.assert_allclose(A, [2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 0.5, 0.5], rtol=1e-15)
+
+
 def test_mesh_sizes_and_areas():
     for s, n in [(0, 12), (1, 42), (2, 162), (3, 642)]:
         w = synth.get("dense-f64-642").with_(subdiv=s)
