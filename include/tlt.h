@@ -170,8 +170,9 @@ tlt_status tlt_build_rows(int32_t n_vertices, int32_t n_cols, int32_t K, int32_t
  * Layout.  The rows are always kept as (column, value) pairs (the plain
  * form).  Unless layout is ROWS or the storage is F64, the library also
  * re-encodes them as block-dense tiles: V Morton-consecutive vertices
- * (V*K rows: 48..128, a multiple of 16; tile_vertices, or by default
- * 48..64 rows for F32 storage and up to 128 for 16-bit storage) share the
+ * (V*K rows: 48..128 and a multiple of 16, or 256 with 16-bit storage;
+ * tile_vertices, or by default 48..64 rows for F32 storage and up to 128
+ * for 16-bit storage) share the
  * sorted union of their kept columns and are stored densely over it
  * (zeros where a row did not keep a column), in the
  * operand order of the 16x16 matrix instructions.  Both layouts hold the
@@ -467,7 +468,8 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                + IPT with MTW m-tiles per wave, NT
  *                                16-column tiles per group and IPT staged
  *                                items per thread: 231 (built-in), 241,
- *                                432 or 442
+ *                                432 or 442; of 16 m-tiles (256 rows): 231
+ *                                (built-in) or 241
  *   TLT_TUNE_IRRADIANCE_HAAR     1 = compute Ehat per frame as the Haar
  *                                transform of A o (T L); 0 (default) = as
  *                                G L with G = H pad(A o T) formed once, for

@@ -35,10 +35,13 @@ def workload_key(w) -> str:
     return key_of(w.storage, w.K, 3 * w.n_out, w.n_vertices, w.n_keep)
 
 
-def vertex_candidates(K: int) -> list:
-    """Tile block sizes the tile kernel supports: V*K rows, 48..128, a
-    multiple of 16."""
-    return [V for V in range(1, 129) if (V * K) % 16 == 0 and 48 <= V * K <= 128]
+def vertex_candidates(K: int, storage: str = "f32") -> list:
+    """Tile block sizes the tile kernel supports: V*K rows, 48..128 and a
+    multiple of 16, or 256 rows with 16-bit storage."""
+    vs = [V for V in range(1, 129) if (V * K) % 16 == 0 and 48 <= V * K <= 128]
+    if storage != "f32" and 256 % K == 0:
+        vs.append(256 // K)
+    return vs
 
 
 def chunk_candidates(storage: str) -> list:
@@ -47,9 +50,12 @@ def chunk_candidates(storage: str) -> list:
 
 
 def shape_candidates(storage: str, rows: int) -> list:
-    """Wave shapes of 16-bit tiles with eight 16-row m-tiles (0 = built-in:
-    two m-tiles and three 16-column tiles per wave); other tiles have one."""
-    return [0, 241, 432] if storage != "f32" and rows == 128 else [0]
+    """Wave shapes of 16-bit tiles with eight or sixteen 16-row m-tiles
+    (0 = built-in: two m-tiles and three 16-column tiles per wave); other
+    tiles have one."""
+    if storage == "f32":
+        return [0]
+    return [0, 241, 432] if rows == 128 else [0, 241] if rows == 256 else [0]
 
 
 def load_table(path: str = TABLE) -> dict:
@@ -97,7 +103,7 @@ def tune(w, device: int = 0, steps: int = 64, log=print) -> dict:
     th = torch.tensor(synth.make_materials(w), dtype=torch.float64, device=dev)
     B = torch.empty((w.n_out, w.n_vertices, 3), dtype=torch.float32, device=dev)
     results = []
-    for V in vertex_candidates(w.K):
+    for V in vertex_candidates(w.K, w.storage):
         r = Renderer(device)
         try:
             r.load_transport(scene, w.n_keep, storage=w.storage, wavelet=w.wavelet,

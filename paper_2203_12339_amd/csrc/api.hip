@@ -845,7 +845,8 @@ TilePlan tile_plan(const tlt_transport_desc *d, int n_cols) {
   TilePlan t;
   t.tV = d->tile_vertices > 0 ? d->tile_vertices : auto_tile_vertices(d->K, d->value_dtype);
   // (the tile build keeps two bitmaps of n_cols bits in LDS)
-  t.ok = t.tV > 0 && t.tV * d->K >= 48 && t.tV * d->K <= 128 && (t.tV * d->K) % 16 == 0 &&
+  t.ok = t.tV > 0 && t.tV * d->K >= 48 && t.tV * d->K <= tile_max_rows(d->value_dtype) &&
+         (t.tV * d->K) % 16 == 0 &&
          (size_t)8 * ((n_cols + 31) / 32) <= (size_t)150 * 1024;
   t.want = d->value_dtype != TLT_F64 && d->layout != TLT_LAYOUT_ROWS && t.ok;
   return t;
@@ -886,7 +887,8 @@ tlt_status check_transport_desc(const tlt_transport_desc *d, std::string *err) {
   const TilePlan tp = tile_plan(d, n_cols);
   if (d->layout == TLT_LAYOUT_TILES && (d->value_dtype == TLT_F64 || !tp.ok))
     return fail(err, TLT_E_ARG,
-                "tiles need non-F64 storage, 48 <= V*K <= 128, V*K % 16 == 0 and at most 614400 columns");
+                "tiles need non-F64 storage, 48 <= V*K <= 128 (256 for 16-bit storage), V*K % 16 == 0 "
+                "and at most 614400 columns");
   if (!d->col) {
     // limits of the device build of the rows
     if (d->n_keep != n_cols && d->n_keep > build_sort_max())

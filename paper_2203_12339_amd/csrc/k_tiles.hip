@@ -485,6 +485,15 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
     if (cmax <= 8) return tiles_go<KIND, 1, 1, 16, 8, 8>(a, nt, st);
     return tiles_go<KIND, 1, 1, 16, 8, 16>(a, nt, st);
   } else {
+    if (MT == 16) {
+      // 256-row blocks (16-bit storage): eight waves of two m-tiles share
+      // each staged irradiance row, so the gathered bytes per W byte halve
+      // against 128-row blocks
+      if (ntw == 1) return tiles_go<KIND, 2, 1, 4, 1>(a, nt, st);
+      if (ntw == 2) return tiles_go<KIND, 2, 2, 4, 1>(a, nt, st);
+      if (a.shape == 241) return tiles_go<KIND, 2, 4, 4, 1>(a, nt, st);
+      return tiles_go<KIND, 2, 3, 4, 1>(a, nt, st);
+    }
     if (MT == 8) {
       // tuned shapes: more m-tiles per wave halve the LDS reads of the
       // staged irradiance per matrix instruction; four n-tiles per group
@@ -507,8 +516,12 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
 
 int tile_kstep(int vdt) { return vdt == 1 ? 4 : 32; }
 
+int tile_max_rows(int vdt) { return vdt == 1 ? 128 : 256; }
+
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st) {
-  if (a.R % 16 != 0 || a.R < 48 || a.R > 128 || a.n_blocks <= 0) return hipErrorInvalidValue;
+  if (a.R % 16 != 0 || a.R < 48 || a.R > tile_max_rows(vdt) || a.n_blocks <= 0)
+    return hipErrorInvalidValue;
+  if (a.R > 128 && a.R != 256) return hipErrorInvalidValue;
   switch (vdt) {
     case 1: return tiles_kind<0>(a, st);
     case 2: return tiles_kind<1>(a, st);

@@ -119,6 +119,8 @@ struct TileArgs {
 };
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
+// Largest block (rows V*K) the tile kernel takes for a storage type.
+int tile_max_rows(int vdt);
 // Zeroed bytes allocated after the tile values: the W register ring of the
 // last block reads up to 2*PD - 1 steps (at most 62 KB) past its end.
 // launch_tiles refuses a shape whose ring would reach further.

@@ -509,17 +509,21 @@ def test_error_paths_on_device():
     r.close()
 
 
-@pytest.mark.parametrize("name,kw", [("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=16, n_cfg=16)),
-                                     ("large-f16-163842:shrunk-128rows",
-                                      dict(subdiv=4, n_light=2, n_cfg=1, sample_rows=0))],
-                         ids=["bf16", "f16"])
-def test_tile_wave_shapes_match_oracle(name, kw):
-    """Every wave shape the tuner may pick for 16-bit blocks of 128 rows
-    renders the oracle's result (C = 48 and 6 columns: full and partial
-    column groups)."""
+@pytest.mark.parametrize("name,kw,rows", [("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=16, n_cfg=16), 128),
+                                          ("large-f16-163842:shrunk-128rows",
+                                           dict(subdiv=4, n_light=2, n_cfg=1, sample_rows=0), 128),
+                                          ("batch64-bf16-40962:shrunk-256rows",
+                                           dict(subdiv=4, n_light=22, n_cfg=22), 256),
+                                          ("large-f16-163842:shrunk-256rows",
+                                           dict(subdiv=4, n_light=2, n_cfg=1, sample_rows=0), 256)],
+                         ids=["bf16", "f16", "bf16-256rows", "f16-256rows"])
+def test_tile_wave_shapes_match_oracle(name, kw, rows):
+    """Every wave shape the tuner may pick for 16-bit blocks of 128 and 256
+    rows renders the oracle's result (C = 48, 66 and 6 columns: full and
+    partial column groups)."""
     from paper_2203_12339_amd import autotune
     w = _workload(name, kw)
-    V = 128 // w.K
+    V = rows // w.K
     say(f"[shapes] {name}: V={V} C={3 * w.n_out}")
     L = synth.make_lighting(w)
     th = synth.make_materials(w)
