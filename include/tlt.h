@@ -442,6 +442,14 @@ tlt_status render_backward_noalloc(tlt_ctx *ctx, const void *dB_dev, void *dSH_d
  */
 tlt_status tlt_read_rows(tlt_ctx *ctx, int64_t n_rows, const int64_t *rows,
                          int32_t *col_out, double *val_out);
+/*
+ * Shape of the loaded tiles (each pointer may be NULL): vertices per block,
+ * blocks, entries (union slots, padded to the k-step), stored 16-row
+ * fragments, bytes of stored values, and 1 when the tiles are
+ * fragment-sparse (TLT_TUNE_TILE_SPARSE).  TLT_E_STATE without tiles.
+ */
+tlt_status tlt_tile_info(tlt_ctx *ctx, int32_t *vertices, int64_t *blocks, int64_t *entries,
+                         int64_t *fragments, int64_t *value_bytes, int32_t *sparse);
 tlt_status tlt_read_state(tlt_ctx *ctx, int which, void *out, size_t *bytes,
                           int *c_stride);
 
@@ -489,6 +497,16 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                coarsest columns (applies at the next
  *                                load_transport; changes results within
  *                                the BF16 storage error)
+ *   TLT_TUNE_TILE_SPARSE         form of the tiles: 1 = dense (rows (o, k),
+ *                                entries in column order, every 16-row
+ *                                fragment stored); 2 = fragment-sparse
+ *                                (rows (k, o), entries ordered by the rows
+ *                                that keep them, fragments without a kept
+ *                                coefficient left out); 0 (default) =
+ *                                sparse for blocks of 256 rows of 16-bit
+ *                                storage, else dense (applies at the next
+ *                                load_transport; float32 summation order
+ *                                only)
  * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
  * key or a value out of range.  Results do not depend on the tuning beyond
  * float32 summation order.
@@ -504,7 +522,8 @@ enum {
   TLT_TUNE_SPATIAL_SEGMENT = 8,
   TLT_TUNE_TILE_SHAPE = 9,
   TLT_TUNE_IRRADIANCE_HAAR = 10,
-  TLT_TUNE_BF16_HEAD = 11
+  TLT_TUNE_BF16_HEAD = 11,
+  TLT_TUNE_TILE_SPARSE = 12
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 

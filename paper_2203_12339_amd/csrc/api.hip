@@ -112,13 +112,18 @@ struct tlt_ctx {
   void *scratch_dev = nullptr;   // this device's copy of the static adjoint scratch
   int n_chunks = 0, ch_rows = 0;
 
-  // block-dense tiles (see tlt.h): offsets, union columns, values
+  // fragment-sparse tiles (see tlt.h): entry and fragment offsets, entry
+  // columns, per-step m-tile masks, stored fragments
   bool tiles = false;
   int tV = 0, tR = 0, t_blocks = 0, t_max_union = 0;
-  int64_t *t_off = nullptr;
+  int64_t *t_off = nullptr, *t_foff = nullptr;
   int32_t *t_ucol = nullptr;
+  uint16_t *t_mask = nullptr;
   void *t_val = nullptr;
   size_t t_val_bytes = 0;
+  int64_t t_frags = 0;   // stored fragments
+  bool t_sparse = false;     // fragment-sparse tiles (rows (k, o), step masks)
+  int tune_tile_sparse = 0;  // 0 built-in, 1 dense, 2 fragment-sparse
 
   // spatially compressed transport (load_spatial): CSR of the kept entries
   // of Z_k = w_1 W_k^S over u, as work items of at most 2048 entries
@@ -266,8 +271,11 @@ void free_all(tlt_ctx *c) {
   c->n_waves = 0;   // the partition belongs to the freed transport
   c->part_rows = 0;
   dfree(c->t_off);
+  dfree(c->t_foff);
   dfree(c->t_ucol);
+  dfree(c->t_mask);
   dfree(c->t_val);
+  c->t_frags = 0;
   c->tiles = false;
   c->t_blocks = 0;
   c->have_P = false;
@@ -410,6 +418,8 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   std::memset(&a, 0, sizeof(a));
   a.blk_off = c->t_off;
   a.ucol = c->t_ucol;
+  a.fmask = c->t_mask;
+  a.foff = c->t_foff;
   a.val = c->t_val;
   a.V = c->tV;
   a.K = c->K;
@@ -429,6 +439,7 @@ TileArgs tile_args(tlt_ctx *c, const void *ehat, const void *ehat2, int Cs, int 
   a.kc = c->tune_tile_chunk;
   a.shape = c->tune_tile_shape;
   a.stream_w = c->t_val_bytes > ((size_t)256 << 20);   // MI355X Infinity Cache: 256 MB
+  a.sparse = c->t_sparse;
   return a;
 }
 
@@ -776,8 +787,9 @@ out:
   return s;
 }
 
-// Block-dense tiles from the device rows: union sizes per block, offsets on
-// the host, then union ids and operand-ordered values.
+// Fragment-sparse tiles from the device rows: entry and fragment counts per
+// block, offsets on the host, then entry ids, step masks and the stored
+// fragments.
 tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   const int nb = (c->N + tV - 1) / tV;
   TileBuildArgs a{};
@@ -793,32 +805,59 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   a.kstep = tile_kstep(c->vdt);
   a.res = c->build_res;
   a.head_cols = c->build_res ? c->head_cols : 0;
-  int64_t *cnt = nullptr, *off = nullptr;
+  // fragment-sparse tiles where they pay (measured): blocks of 256 rows of
+  // 16-bit storage, whose W stream bounds the product; smaller blocks are
+  // bound by their matrix work, which the sparse form cannot shorten (a
+  // workgroup's waves wait for the fullest one at every staged chunk)
+  {
+    const bool want = c->tune_tile_sparse == 2 ||
+                      (c->tune_tile_sparse == 0 && c->vdt != TLT_F32 && tV * c->K == 256);
+    a.order = want && tile_build_lds(a.n_words, true) <= (size_t)150 * 1024;
+  }
+  int64_t *cnt = nullptr, *fcnt = nullptr;
+  size_t val_alloc = 0;
   tlt_status s = TLT_OK;
   hipError_t he = hipSuccess;
-  std::vector<int64_t> h(nb), ho(nb + 1, 0);
+  const int kpl = a.kstep / 4;
+  std::vector<int64_t> h(nb), hf(nb), ho(nb + 1, 0), fo(nb + 1, 0);
   if ((s = dalloc(c, (void **)&cnt, sizeof(int64_t) * nb, "tile counts")) != TLT_OK) return s;
+  if ((s = dalloc(c, (void **)&fcnt, sizeof(int64_t) * nb, "tile fragment counts")) != TLT_OK) goto out;
 #define BTRY(x) if ((he = (x)) != hipSuccess) { s = hip_fail(c, he, #x); goto out; }
   a.count = cnt;
+  a.fcount = fcnt;
   BTRY(launch_tile_count(a, 0));
   BTRY(hipMemcpy(h.data(), cnt, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
+  BTRY(hipMemcpy(hf.data(), fcnt, sizeof(int64_t) * nb, hipMemcpyDeviceToHost));
   c->t_max_union = 0;
   for (int b = 0; b < nb; ++b) {
     ho[b + 1] = ho[b] + h[b];
+    fo[b + 1] = fo[b] + hf[b];
     c->t_max_union = std::max<int>(c->t_max_union, (int)h[b]);
+    if (h[b] % a.kstep != 0 || hf[b] < 1 || hf[b] > h[b] / a.kstep * (tV * c->K / 16)) {
+      s = fail(&c->err, TLT_E_STATE, "tile build: inconsistent entry or fragment count");
+      goto out;
+    }
   }
   c->tV = tV;
   c->tR = tV * c->K;
   c->t_blocks = nb;
-  // (the zeroed slack after the last block is read by its W ring)
-  c->t_val_bytes = (size_t)ho[nb] * c->tR * a.esz + TILE_VAL_SLACK;
+  c->t_frags = fo[nb];
+  c->t_sparse = a.order;
+  c->t_val_bytes = (size_t)fo[nb] * 64 * kpl * a.esz;
   if ((s = dalloc(c, (void **)&c->t_off, sizeof(int64_t) * (nb + 1), "tile offsets")) != TLT_OK) goto out;
+  if ((s = dalloc(c, (void **)&c->t_foff, sizeof(int64_t) * (nb + 1), "tile fragment offsets")) != TLT_OK) goto out;
   if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * (size_t)ho[nb], "tile columns")) != TLT_OK) goto out;
-  if ((s = dalloc(c, &c->t_val, c->t_val_bytes, "tile values")) != TLT_OK) goto out;
+  if ((s = dalloc(c, (void **)&c->t_mask, sizeof(uint16_t) * (size_t)(ho[nb] / a.kstep), "tile masks")) != TLT_OK) goto out;
+  // dense blocks: zeroed slack after the last block, read by its W ring
+  val_alloc = c->t_val_bytes + (a.order ? 0 : TILE_VAL_SLACK);
+  if ((s = dalloc(c, &c->t_val, val_alloc, "tile values")) != TLT_OK) goto out;
   BTRY(hipMemcpy(c->t_off, ho.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
-  BTRY(hipMemset(c->t_val, 0, c->t_val_bytes));
+  BTRY(hipMemcpy(c->t_foff, fo.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
+  BTRY(hipMemset(c->t_val, 0, val_alloc));
   a.blk_off = c->t_off;
+  a.frag_off = c->t_foff;
   a.ucol = c->t_ucol;
+  a.mask = c->t_mask;
   a.tval = c->t_val;
   BTRY(launch_tile_fill(a, 0));
   BTRY(hipDeviceSynchronize());
@@ -826,7 +865,7 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
 #undef BTRY
 out:
   dfree(cnt);
-  (void)off;
+  dfree(fcnt);
   return s;
 }
 
@@ -1501,6 +1540,10 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
       if (value > 1) return fail(&c->err, TLT_E_ARG, "BF16 head flag must be 0 or 1");
       c->tune_head_off = value;
       break;
+    case TLT_TUNE_TILE_SPARSE:
+      if (value > 2) return fail(&c->err, TLT_E_ARG, "tile form must be 0, 1 or 2");
+      c->tune_tile_sparse = value;
+      break;
     case TLT_TUNE_IRRADIANCE_HAAR:
       if (value > 1) return fail(&c->err, TLT_E_ARG, "irradiance flag must be 0 or 1");
       c->tune_irr_haar = value;
@@ -1594,6 +1637,23 @@ tlt_status tlt_read_rows(tlt_ctx *c, int64_t n_rows, const int64_t *rows, int32_
     HIPC(c, hipMemcpy(raw.data(), (char *)c->val + off * vsz, vsz * c->n_keep, hipMemcpyDeviceToHost));
     for (int64_t e = 0; e < c->n_keep; ++e) val_out[i * c->n_keep + e] = widen(raw.data(), c->vdt, e);
   }
+  return TLT_OK;
+}
+
+tlt_status tlt_tile_info(tlt_ctx *c, int32_t *vertices, int64_t *blocks, int64_t *entries,
+                         int64_t *fragments, int64_t *value_bytes, int32_t *sparse) {
+  if (!c) return fail(nullptr, TLT_E_ARG, "ctx is NULL");
+  if (!c->loaded || !c->tiles) return fail(&c->err, TLT_E_STATE, "no tiles loaded");
+  if (vertices) *vertices = c->tV;
+  if (blocks) *blocks = c->t_blocks;
+  if (entries) {
+    int64_t n = 0;
+    HIPC(c, hipMemcpy(&n, c->t_off + c->t_blocks, sizeof(int64_t), hipMemcpyDeviceToHost));
+    *entries = n;
+  }
+  if (fragments) *fragments = c->t_frags;
+  if (value_bytes) *value_bytes = (int64_t)c->t_val_bytes;
+  if (sparse) *sparse = c->t_sparse ? 1 : 0;
   return TLT_OK;
 }
 

@@ -519,69 +519,98 @@ __global__ __launch_bounds__(256) void k_build_sort(BuildArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Block-dense tiles from the (column, value) rows: the union of the kept
-// columns of a block's rows as a bitmap, its size (count pass), then the
-// union ids and the values scattered into the matrix-instruction operand
-// order (fill pass).
+// Fragment-sparse tiles from the (column, value) rows.  Per block (one
+// workgroup): the union of the kept columns of its rows as a bitmap; the
+// union entries (and, with residuals, the head columns once more); the
+// m-tiles (16-row groups, rows ordered (k, o)) that keep each entry; the
+// entries ordered by (first m-tile, last m-tile, entry) so that the entries
+// kept by the same m-tiles sit in the same k-steps; then, per k-step, the
+// mask of m-tiles with a kept entry in it.  Only those (k-step, m-tile)
+// fragments are stored.  The count pass gives the padded entry count and
+// the fragment count of every block, the fill pass (same ordering) writes
+// the union ids, the masks and the values.  Unions above TB_UL entries
+// (or with ordering off) keep column order and store every fragment.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void block_bitmap(const TileBuildArgs &a, int b, uint32_t *bm) {
+constexpr int TB_UL = 8192;   // largest union ordered by m-tile pattern
+
+constexpr int TB_STEPS = TB_UL / 4;   // k-steps of an ordered union (k-step >= 4)
+
+// LDS layout of the build: bm, pref [n_words] u32; then, when ordering,
+// pat [TB_UL/2] u32 (16-bit patterns), key [TB_UL] u32, pos [TB_UL/2] u32
+// (16-bit positions), mask [TB_STEPS] u16, fpref [TB_STEPS] u32 (fragments
+// before each step).
+size_t tile_build_lds(int n_words, bool order) {
+  size_t b = 2 * sizeof(uint32_t) * (size_t)n_words;
+  if (order) b += sizeof(uint32_t) * (TB_UL / 2 + TB_UL + TB_UL / 2) + 6 * TB_STEPS;
+  return b;
+}
+
+struct TileOrder {
+  uint32_t *bm, *pref, *pat, *key, *pos, *fpref;
+  uint16_t *mask;
+  int U0, H, U, n_steps, MT;
+  bool ordered;
+  uint32_t frags;   // fragments stored
+};
+
+// Column of union entry e (< U0 + H) from the bitmap: the e-th set bit
+// (entries >= U0 are the residuals of the first entries).  Only used for
+// the few head entries.
+__device__ __forceinline__ int union_col_of(const TileOrder &o, const TileBuildArgs &a, int e) {
+  if (e >= o.U0) e -= o.U0;
+  for (int w = 0; w < a.n_words; ++w) {
+    const int c = __popc(o.bm[w]);
+    if (e < c) {
+      uint32_t bits = o.bm[w];
+      for (int i = 0; i < e; ++i) bits &= bits - 1u;
+      return 32 * w + __ffs(bits) - 1;
+    }
+    e -= c;
+  }
+  return 0;
+}
+
+__device__ __forceinline__ int rank_of(const TileOrder &o, int j) {
+  return (int)(o.pref[j >> 5] + (uint32_t)__popc(o.bm[j >> 5] & ((1u << (j & 31)) - 1u)));
+}
+
+// Row of the block for vertex offset vl and term k: (k, o) order for
+// fragment-sparse tiles, (o, k) for dense ones.
+__device__ __forceinline__ int tile_row(const TileBuildArgs &a, int vl, int k) {
+  return a.order ? k * a.V + vl : vl * a.K + k;
+}
+
+__device__ void block_order(const TileBuildArgs &a, int b, unsigned char *smem, TileOrder &o) {
   const int t = threadIdx.x;
-  for (int w = t; w < a.n_words; w += blockDim.x) bm[w] = 0u;
+  const int R = a.V * a.K, ks = a.kstep;
+  o.MT = R / 16;
+  o.bm = reinterpret_cast<uint32_t *>(smem);
+  o.pref = o.bm + a.n_words;
+  uint32_t *tail = o.pref + a.n_words;
+  o.pat = tail;
+  o.key = o.pat + TB_UL / 2;
+  o.pos = o.key + TB_UL;
+  o.mask = reinterpret_cast<uint16_t *>(o.pos + TB_UL / 2);
+  o.fpref = reinterpret_cast<uint32_t *>(o.mask + TB_STEPS);
+  __shared__ uint32_t tsum[256];
+  __shared__ uint32_t s_total, s_frags;
+  // bitmap of the kept columns
+  for (int w = t; w < a.n_words; w += 256) o.bm[w] = 0u;
   __syncthreads();
   const int v0 = b * a.V, v1 = min(a.N, v0 + a.V);
   const int64_t e0 = (int64_t)v0 * a.K * a.n_keep, e1 = (int64_t)v1 * a.K * a.n_keep;
-  for (int64_t e = e0 + t; e < e1; e += blockDim.x) {
+  for (int64_t e = e0 + t; e < e1; e += 256) {
     const int j = a.col[e];
-    atomicOr(&bm[j >> 5], 1u << (j & 31));
+    atomicOr(&o.bm[j >> 5], 1u << (j & 31));
   }
   __syncthreads();
-}
-
-// Union columns below head_cols (the first words of the bitmap).
-__device__ __forceinline__ uint32_t head_count(const TileBuildArgs &a, const uint32_t *bm) {
-  if (a.res == nullptr) return 0u;
-  uint32_t h = 0;
-  for (int w = 0; w * 32 < a.head_cols; ++w) {
-    const int nb = min(32, a.head_cols - 32 * w);
-    h += (uint32_t)__popc(bm[w] & (nb == 32 ? 0xffffffffu : ((1u << nb) - 1u)));
-  }
-  return h;
-}
-
-__global__ __launch_bounds__(256) void k_tile_count(TileBuildArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
-  __shared__ uint32_t total;
-  const int b = blockIdx.x;
-  if (threadIdx.x == 0) total = 0u;
-  block_bitmap(a, b, bm);
-  uint32_t c = 0;
-  for (int w = threadIdx.x; w < a.n_words; w += blockDim.x) c += (uint32_t)__popc(bm[w]);
-  c = wave_sum(c);
-  if ((threadIdx.x & 63) == 0) atomicAdd(&total, c);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t n = total + head_count(a, bm);
-    a.count[b] = (int64_t)((n + a.kstep - 1) / a.kstep * a.kstep);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t *bm = reinterpret_cast<uint32_t *>(smem);
-  uint32_t *pref = bm + a.n_words;
-  __shared__ uint32_t tsum[256];
-  __shared__ uint32_t total;
-  const int b = blockIdx.x;
-  const int t = threadIdx.x;
-  block_bitmap(a, b, bm);
   // exclusive prefix of the word popcounts: contiguous word ranges per thread
   const int per = (a.n_words + 255) / 256;
   const int w0 = min(a.n_words, t * per), w1 = min(a.n_words, w0 + per);
-  uint32_t s = 0;
-  for (int w = w0; w < w1; ++w) s += (uint32_t)__popc(bm[w]);
-  tsum[t] = s;
+  uint32_t sum = 0;
+  for (int w = w0; w < w1; ++w) sum += (uint32_t)__popc(o.bm[w]);
+  tsum[t] = sum;
   __syncthreads();
   if (t == 0) {
     uint32_t acc = 0;
@@ -590,57 +619,179 @@ __global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
       tsum[i] = acc;
       acc += x;
     }
-    total = acc;
+    s_total = acc;
   }
   __syncthreads();
-  s = tsum[t];
+  sum = tsum[t];
   for (int w = w0; w < w1; ++w) {
-    pref[w] = s;
-    s += (uint32_t)__popc(bm[w]);
+    o.pref[w] = sum;
+    sum += (uint32_t)__popc(o.bm[w]);
+  }
+  o.U0 = (int)s_total;
+  // residual entries: the union's columns below head_cols (its first H entries)
+  o.H = 0;
+  if (a.res != nullptr)
+    for (int w = 0; w * 32 < a.head_cols; ++w) {
+      const int nb = min(32, a.head_cols - 32 * w);
+      o.H += __popc(o.bm[w] & (nb == 32 ? 0xffffffffu : ((1u << nb) - 1u)));
+    }
+  o.U = o.U0 + o.H;
+  o.n_steps = (o.U + ks - 1) / ks;
+  o.ordered = a.order && o.U <= TB_UL && o.MT <= 16;
+  __syncthreads();
+  if (!o.ordered) {
+    o.frags = (uint32_t)o.n_steps * o.MT;
+    return;
+  }
+  // m-tile patterns of the entries (16 bits each, two per word)
+  for (int i = t; i < TB_UL / 2; i += 256) o.pat[i] = 0u;
+  __syncthreads();
+  for (int64_t e = e0 + t; e < e1; e += 256) {
+    const int j = a.col[e];
+    const int rk = (int)((e - e0) / a.n_keep);            // (o, k) row of the input
+    const int r = tile_row(a, rk / a.K, rk % a.K);
+    const int u = rank_of(o, j);
+    atomicOr(&o.pat[u >> 1], (1u << (r >> 4)) << (16 * (u & 1)));
   }
   __syncthreads();
+  auto pat_of = [&](int e) -> uint32_t {
+    const int u = e >= o.U0 ? e - o.U0 : e;
+    return (o.pat[u >> 1] >> (16 * (u & 1))) & 0xffffu;
+  };
+  // sort keys (first m-tile, last m-tile, entry), padded to a power of two
+  int P2 = 1;
+  while (P2 < o.U) P2 <<= 1;
+  for (int i = t; i < P2; i += 256) {
+    uint32_t k = 0xffffffffu;
+    if (i < o.U) {
+      const uint32_t pt = pat_of(i);
+      const uint32_t first = (uint32_t)__ffs(pt) - 1u, last = 31u - (uint32_t)__clz(pt);
+      k = ((first * 16u + last) << 20) | (uint32_t)i;
+    }
+    o.key[i] = k;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= P2; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      for (int i = t; i < P2; i += 256) {
+        const int l = i ^ jj;
+        if (l > i) {
+          const uint32_t x = o.key[i], y = o.key[l];
+          const bool asc = (i & kk) == 0;
+          if ((x > y) == asc) {
+            o.key[i] = y;
+            o.key[l] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // position of every entry; mask of every k-step
+  for (int i = t; i < TB_UL / 2; i += 256) o.pos[i] = 0u;
+  __syncthreads();
+  for (int p = t; p < o.U; p += 256) {
+    const int e = (int)(o.key[p] & 0xfffffu);
+    atomicOr(&o.pos[e >> 1], (uint32_t)p << (16 * (e & 1)));
+  }
+  for (int s = t; s < o.n_steps; s += 256) {
+    uint32_t m = 0;
+    for (int p = s * ks; p < min(o.U, (s + 1) * ks); ++p) m |= pat_of((int)(o.key[p] & 0xfffffu));
+    o.mask[s] = (uint16_t)m;
+  }
+  __syncthreads();
+  if (t == 0) {
+    uint32_t acc = 0;
+    for (int s = 0; s < o.n_steps; ++s) {
+      o.fpref[s] = acc;
+      acc += (uint32_t)__popc((uint32_t)o.mask[s]);
+    }
+    s_frags = acc;
+  }
+  __syncthreads();
+  o.frags = s_frags;
+}
+
+__device__ __forceinline__ int pos_of(const TileOrder &o, int e) {
+  return o.ordered ? (int)((o.pos[e >> 1] >> (16 * (e & 1))) & 0xffffu) : e;
+}
+
+__global__ __launch_bounds__(256) void k_tile_count(TileBuildArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TileOrder o;
+  block_order(a, blockIdx.x, smem, o);
+  if (threadIdx.x == 0) {
+    a.count[blockIdx.x] = (int64_t)o.n_steps * a.kstep;
+    a.fcount[blockIdx.x] = (int64_t)o.frags;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_fill(TileBuildArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  TileOrder o;
+  const int b = blockIdx.x;
+  const int t = threadIdx.x;
+  block_order(a, b, smem, o);
   const int64_t off = a.blk_off[b];
-  const int64_t nu = a.blk_off[b + 1] - off;
-  // union column ids (ascending), then the padding (column 0, zero values)
+  const int64_t nu = a.blk_off[b + 1] - off;           // n_steps * kstep
+  const int64_t fo = a.frag_off[b];
+  const uint32_t nf = (uint32_t)(a.frag_off[b + 1] - fo);
+  const int ks = a.kstep, kpl = ks / 4, MT = o.MT;
+  // union ids at their positions; padding entries read column 0
+  const int per = (a.n_words + 255) / 256;
+  const int w0 = min(a.n_words, t * per), w1 = min(a.n_words, w0 + per);
   for (int w = w0; w < w1; ++w) {
-    uint32_t bits = bm[w];
-    uint32_t u = pref[w];
+    uint32_t bits = o.bm[w];
+    int u = (int)o.pref[w];
     while (bits) {
       const int bit = __ffs(bits) - 1;
-      a.ucol[off + u] = 32 * w + bit;
+      const int p = pos_of(o, u);
+      if (p < nu) a.ucol[off + p] = 32 * w + bit;
       ++u;
       bits &= bits - 1u;
     }
   }
-  // the head columns once more (residual entries), then the padding
-  const uint32_t hb = head_count(a, bm);
-  if (t < a.head_cols && a.res != nullptr && ((bm[t >> 5] >> (t & 31)) & 1u))
-    a.ucol[off + total + (uint32_t)__popc(bm[t >> 5] & ((1u << (t & 31)) - 1u)) + (t >= 32 ? (uint32_t)__popc(bm[0]) : 0u)] = t;
-  for (int64_t u = total + hb + t; u < nu; u += 256) a.ucol[off + u] = 0;
-  // values in operand order
-  const int R = a.V * a.K, MT = R / 16, ks = a.kstep, kpl = ks / 4;
+  for (int h = t; h < o.H; h += 256) {
+    const int p = pos_of(o, o.U0 + h);
+    if (p < nu) a.ucol[off + p] = union_col_of(o, a, h);
+  }
+  for (int64_t p = o.U + t; p < nu; p += 256) a.ucol[off + p] = 0;
+  // step masks
+  const int64_t s0 = off / ks;
+  for (int s = t; s < o.n_steps; s += 256)
+    a.mask[s0 + s] = o.ordered ? o.mask[s] : (uint16_t)((1u << MT) - 1u);
+  // values: fragment (step, m-tile) stored at its rank among the block's
+  // stored fragments; lane l holds rows 16 m + l % 16, elements
+  // kpl (l / 16) .. of the step
   const int v0 = b * a.V, v1 = min(a.N, v0 + a.V);
   const int64_t e0 = (int64_t)v0 * a.K * a.n_keep, e1 = (int64_t)v1 * a.K * a.n_keep;
+  auto put = [&](int p, int r, uint32_t word) {
+    const int st = p / ks, rem = p % ks, m = r >> 4;
+    uint32_t f;
+    if (o.ordered) {
+      const uint32_t msk = o.mask[st];
+      if (!((msk >> m) & 1u)) return;   // cannot happen: the entry's pattern has bit m
+      f = o.fpref[st] + (uint32_t)__popc(msk & ((1u << m) - 1u));
+    } else {
+      f = (uint32_t)st * MT + m;
+    }
+    if (f >= nf) return;
+    const int lane = (rem / kpl) * 16 + (r & 15);
+    const int64_t w = ((fo + f) * 64 + lane) * kpl + rem % kpl;
+    if (a.esz == 4)
+      ((uint32_t *)a.tval)[w] = word;
+    else
+      ((uint16_t *)a.tval)[w] = (uint16_t)word;
+  };
   for (int64_t e = e0 + t; e < e1; e += 256) {
     const int j = a.col[e];
-    const int row = (int)((e - e0) / a.n_keep);
-    const uint32_t word = bm[j >> 5];
-    const int u = (int)(pref[j >> 5] + (uint32_t)__popc(word & ((1u << (j & 31)) - 1u)));
-    const int st = u / ks, rem = u % ks;
-    const int lane = (rem / kpl) * 16 + (row & 15);
-    const int64_t w = off * R + (((int64_t)st * MT + row / 16) * 64 + lane) * kpl + rem % kpl;
-    if (a.esz == 4)
-      ((uint32_t *)a.tval)[w] = ((const uint32_t *)a.val)[e];
-    else
-      ((uint16_t *)a.tval)[w] = ((const uint16_t *)a.val)[e];
-    if (a.res != nullptr && j < a.head_cols) {
-      // u < head_cols here: the union's entries before u are columns below j
-      const int uh = (int)total + u;
-      const int sh = uh / ks, rh = uh % ks;
-      const int lh = (rh / kpl) * 16 + (row & 15);
-      const int64_t wh = off * R + (((int64_t)sh * MT + row / 16) * 64 + lh) * kpl + rh % kpl;
-      ((uint16_t *)a.tval)[wh] = a.res[e / a.n_keep * a.head_cols + j];
-    }
+    const int rk = (int)((e - e0) / a.n_keep);
+    const int r = tile_row(a, rk / a.K, rk % a.K);
+    const int u = rank_of(o, j);
+    const uint32_t word = a.esz == 4 ? ((const uint32_t *)a.val)[e] : ((const uint16_t *)a.val)[e];
+    put(pos_of(o, u), r, word);
+    if (a.res != nullptr && j < a.head_cols)   // u < H: the residual entry U0 + u
+      put(pos_of(o, o.U0 + u), r, a.res[e / a.n_keep * a.head_cols + j]);
   }
 }
 
@@ -698,15 +849,15 @@ hipError_t launch_quantize_rows(const double *src, const int32_t *col, void *val
 }
 
 hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st) {
-  const size_t lds = sizeof(uint32_t) * (size_t)a.n_words;
+  const size_t lds = tile_build_lds(a.n_words, a.order);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_tile_count, dim3(a.n_blocks), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st) {
-  const size_t lds = 2 * sizeof(uint32_t) * (size_t)a.n_words;
-  if (lds > 150 * 1024) return hipErrorInvalidValue;
+  const size_t lds = tile_build_lds(a.n_words, a.order);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_tile_fill, dim3(a.n_blocks), dim3(256), lds, st, a);
   return hipGetLastError();
 }

@@ -1,16 +1,21 @@
 // Block-dense tiles: the wavelet-sparse transport of Eq. (7)/(8)
 // (rendering Steps 2 and 4 of Sec. 4) as 16x16 matrix-instruction tiles.
 //
-// A block holds the R = V*K rows (o, k) of V Morton-consecutive vertices,
-// dense over the sorted union U of their kept columns (about half of the
-// slots are kept coefficients, the rest zeros).  One workgroup per block
-// (and 16*NT-column group), one wave per 16-row m-tile:
+// A block holds the R = V*K rows of V Morton-consecutive vertices, ordered
+// (k, o), over the union U of their kept columns, ordered so that entries
+// kept by the same rows share k-steps.  Only the (k-step, 16-row m-tile)
+// fragments holding a kept coefficient are stored (dense inside: about
+// half of their slots are kept coefficients, the rest zeros); a 16-bit mask
+// per k-step says which.  One workgroup per block (and 16*NT-column group),
+// waves split the m-tiles:
 //
 //   D[row, c] = sum_u W[row, u] * Ehat[U[u], c]       (MFMA, FP32 accumulate)
-//   B[o, c]   = sum_k g_k[c] * D[(o,k), c]            (K-term fusion)
+//   B[o, c]   = sum_k g_k[c] * D[(k,o), c]            (K-term fusion)
 //
 // W streams from HBM once, in fragment order (one contiguous 256 B or 1 KB
-// load per wave and step).  The gathered irradiance rows Ehat[U[u]] are
+// load per wave, step and stored m-tile; absent fragments are loads past
+// the block's buffer range, which return zeros without a memory access,
+// and their matrix instructions are skipped).  The gathered irradiance rows Ehat[U[u]] are
 // read once per block into LDS, already in B-operand fragment order, and
 // shared by every wave -- each gathered row serves all V*K rows of the
 // block.  With 16-bit storage Ehat is split into hi + lo 16-bit parts (two
@@ -110,7 +115,11 @@ constexpr int TILE_LDS = 64 * 1024;  // staging budget per workgroup
 // 624 -> 694 us at 40962 vertices, 192 columns in three groups), and tiles
 // that fit the Infinity Cache stay there from one render to the next
 // (non-temporal measured 41.8 -> 44.7 us at 10242 vertices, 232 MB).
-template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC, int WAUX>
+// SP: fragment-sparse blocks (rows (k, o), entries in m-tile pattern order,
+// only fragments with a kept coefficient stored, per-step masks); else
+// dense blocks (rows (o, k), entries in column order, every fragment
+// stored, the K rows of a vertex fused in registers).
+template <int KIND, int MTW, int NT, int PD, int IPT, int CGS, int CSC, int WAUX, bool SP>
 __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   typedef TileKind<KIND> TK;
   typedef typename TK::BElem BElem;
@@ -129,7 +138,6 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   const int b = (blockIdx.x & 7) * per_xcd + slot / ng;
   const int grp = slot % ng;
   if (slot / ng >= per_xcd || b >= a.n_blocks) return;
-  const int MT = a.R / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = wave;  // waves split the m-tiles
   const int nthr = blockDim.x;
@@ -137,10 +145,11 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   const int cg = min(NT * 16, a.C - cbase);  // real columns of this group
   const int64_t u0 = a.blk_off[b];
   const int n_steps = (int)((a.blk_off[b + 1] - u0) / KS);
+  const int64_t f0 = a.foff[b];
+  const int n_frags = (int)(a.foff[b + 1] - f0);
   constexpr int CS = CSC;
   const int32_t *__restrict__ ucol = a.ucol + u0;
   const float *__restrict__ ehat = (const float *)a.ehat;
-  const int64_t vbase = u0 * a.R;
 
   // Staging.  The union column ids of the whole block are read into LDS
   // once.  float32: item = (step sl, lane group lg, real column n), one
@@ -151,7 +160,10 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   // of the next chunk are issued into registers before the current chunk's
   // matrix work and stored to LDS after it.
   int *uc = reinterpret_cast<int *>(smem + a.uc_offset);
+  uint16_t *mk = reinterpret_cast<uint16_t *>(smem + a.mk_offset);
   for (int i = threadIdx.x; i < n_steps * KS; i += nthr) uc[i] = ucol[i];
+  if constexpr (SP)
+    for (int i = threadIdx.x; i < n_steps; i += nthr) mk[i] = a.fmask[u0 / KS + i];
   constexpr int QW = KIND == 0 ? 1 : 4;  // columns per item
   const int cq = (cg + QW - 1) / QW;     // items per (step, lane group)
   int it_sl[IPT], it_eoff[IPT], it_col[IPT], it_lds[IPT], it_slot[IPT], it_sw[IPT];
@@ -233,22 +245,49 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[m][nt] = f32x4{0, 0, 0, 0};
 
-  // W fragments for step s of this wave's m-tiles, through a buffer
-  // resource over the block's values: the step is a scalar offset, the lane
-  // a fixed vector offset.  The ring reads up to 2*PD - 1 steps past the
-  // block's end; those steps only ever multiply zero B fragments, and what
-  // they read is finite either way: zeros where the descriptor's bound
-  // clips the access, else the next block's values or, after the last
-  // block, the zeroed slack allocated behind the tile values.
-  const int step_bytes = MT * 64 * KPL * TK::VSZ;
+  // W fragments of this wave's m-tiles, step by step, through a buffer
+  // resource over the block's stored fragments.  The loads run in step order
+  // at a frontier PD steps ahead of the matrix work; fp_load counts the
+  // stored fragments of the steps before the frontier, so the fragment of
+  // (step s, m-tile t) is number fp_load + popcount(mask[s] below t).  An
+  // absent fragment (and every step past the block's end, whose mask reads
+  // as 0) gets an offset past the range, which the buffer bound turns into
+  // zeros without a memory access.  All offsets are in the vector operand,
+  // which the range check covers.
+  constexpr int FRAG = 64 * KPL * TK::VSZ;   // bytes per stored fragment
+  constexpr int OOB = 0x7ffff000;
   const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
-      (void *)((const char *)a.val + vbase * TK::VSZ), (short)0, n_steps * step_bytes, 0x00020000);
-  int loff[MTW];
+      (void *)((const char *)a.val + f0 * FRAG), (short)0, n_frags * FRAG, 0x00020000);
+  const int lane_off = lane * KPL * TK::VSZ;
+  const int tbase = wm * MTW;   // this wave's first m-tile
+  uint32_t fp_load = 0;
+  int s_load = 0;
+  const int MT = a.R / 16;
+  auto step_mask = [&](int s) -> uint32_t {
+    return __builtin_amdgcn_readfirstlane(s < n_steps ? (uint32_t)mk[s] : 0u);
+  };
+  auto load_next = [&](AFrag (&dst)[MTW]) {
+    if constexpr (SP) {
+      const uint32_t ms = step_mask(s_load);
 #pragma unroll
-  for (int m = 0; m < MTW; ++m) loff[m] = ((wm * MTW + m) * 64 + lane) * KPL * TK::VSZ;
-  auto load_a = [&](int s, AFrag (&dst)[MTW]) {
+      for (int m = 0; m < MTW; ++m) {
+        const int t = tbase + m;
+        const uint32_t idx = fp_load + (uint32_t)__popc(ms & ((1u << t) - 1u));
+        const int voff = ((ms >> t) & 1u) ? (int)(idx * FRAG) + lane_off : OOB;
+        dst[m] = TK::template frag<WAUX>(wrs, voff, 0);
+      }
+      fp_load += (uint32_t)__popc(ms);
+    } else {
+      // every fragment stored: (s, t) is number s MT + t.  The step is a
+      // scalar offset, the lane a fixed vector offset; the ring reads up to
+      // 2 PD - 1 steps past the block's end, which only ever multiply zero B
+      // fragments and read finite values: the next block's, or after the
+      // last block the zeroed slack allocated behind the tile values.
 #pragma unroll
-    for (int m = 0; m < MTW; ++m) dst[m] = TK::template frag<WAUX>(wrs, loff[m], s * step_bytes);
+      for (int m = 0; m < MTW; ++m)
+        dst[m] = TK::template frag<WAUX>(wrs, (tbase + m) * FRAG + lane_off, s_load * MT * FRAG);
+    }
+    ++s_load;
   };
   // B fragments of step sl of the staged chunk (unconditional LDS reads).
   // 16-bit kinds: the fragment of (step, column tile nt, half h) holds lane
@@ -275,8 +314,9 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       }
   };
   AFrag ring[PD][MTW];
+  if constexpr (SP) __syncthreads();  // step masks visible
 #pragma unroll
-  for (int p = 0; p < PD; ++p) load_a(p, ring[p]);
+  for (int p = 0; p < PD; ++p) load_next(ring[p]);
 
   int ns = min(CS, n_steps);
   gather(0, ns);
@@ -287,9 +327,11 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     const int ns_next = min(CS, n_steps - nxt);
     if (ns_next > 0) gather(nxt, ns_next);
     // Groups of PD steps: a group runs whole or not at all, so the W ring
-    // stays in step and the load counters can be waited on exactly; steps
-    // of the last group past the chunk's end multiply zero B fragments, and
-    // their W loads fall past the block's end and read zeros.
+    // stays in step (one refill per step, in step order) and the load
+    // counters can be waited on exactly.  A step whose mask has none of the
+    // wave's m-tiles (absent fragments, and the steps of the last group past
+    // the block's end, whose mask is 0) skips its operand reads and matrix
+    // work; only its refill runs.
 #pragma unroll
     for (int g0 = 0; g0 < CS; g0 += PD) {
       if (g0 < ns) {
@@ -305,25 +347,45 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
         for (int p = 0; p < PD; ++p) {
           const int sl = g0 + p;
-          BFrag bf[NT][H];
-          if constexpr (KIND == 0) {
-            bf[0][0] = bg[p];
-          } else {
-            read_b(min(sl, ns - 1), bf);
-            if (sl >= ns) {
+          if constexpr (SP) {
+            const uint32_t wb = (step_mask(s0 + sl) >> tbase) & ((1u << MTW) - 1u);
+            if (wb != 0u) {   // then sl < ns
+              BFrag bf[NT][H];
+              if constexpr (KIND == 0)
+                bf[0][0] = bg[p];
+              else
+                read_b(sl, bf);
 #pragma unroll
               for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int h = 0; h < H; ++h) bf[nt][h] = BFrag{};
+                for (int h = 0; h < H; ++h)
+#pragma unroll
+                  for (int m = 0; m < MTW; ++m)
+                    if ((wb >> m) & 1u) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
             }
+          } else {
+            // dense: steps of the last group past the chunk's end multiply
+            // zero B fragments
+            BFrag bf[NT][H];
+            if constexpr (KIND == 0) {
+              bf[0][0] = bg[p];
+            } else {
+              read_b(min(sl, ns - 1), bf);
+              if (sl >= ns) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                  for (int h = 0; h < H; ++h) bf[nt][h] = BFrag{};
+              }
+            }
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+              for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
           }
-#pragma unroll
-          for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int h = 0; h < H; ++h)
-#pragma unroll
-              for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
-          load_a(s0 + sl + PD, ring[p]);  // refill this slot PD steps ahead
+          load_next(ring[p]);  // refill this slot PD steps ahead
           // keep the refill right behind its step (no regrouping of loads)
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -337,13 +399,20 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     ns = ns_next;
   }
 
-  // ---- epilogue: v_k (optional; row (perm[o], k), vertex-major in original
-  // vertex order) and the K-term fusion into B ----
-  const int K = a.K;
+  // ---- epilogue.  Sparse blocks: rows r = k V + vl; dense blocks: rows
+  // r = vl K + k.  v_k (optional; row (perm[o], k) of vsave, vertices in
+  // original order), then the K-term fusion: B[o, c] = sum over k in order
+  // of g_k[c] D[(o, k), c] -- in registers when the K rows of a vertex sit
+  // in lane groups of one m-tile (dense blocks, K = 4, 8, 16), else through
+  // LDS.
+  const int K = a.K, V = a.V;
   const int lg = lane >> 4, ln = lane & 15;
   const float *gcol = (const float *)a.gcol;
   float *vsave = (float *)a.vsave;
   float *B = (float *)a.B;
+  constexpr int CW = NT * 16;
+  auto row_k = [&](int r) { return SP ? r / V : r % K; };
+  auto row_v = [&](int r) { return SP ? r % V : r / K; };
   if (vsave != nullptr) {
 #pragma unroll
     for (int m = 0; m < MTW; ++m)
@@ -352,16 +421,15 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
         const int c = cbase + nt * 16 + ln;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = (wm * MTW + m) * 16 + 4 * lg + v;
-          const int o = b * a.V + row / K, k = row % K;
+          const int r = (tbase + m) * 16 + 4 * lg + v;
+          const int o = b * V + row_v(r);
           if (c < a.C && o < a.N)
-            vsave[((int64_t)a.perm[o] * K + k) * a.vs_stride + c] = acc[m][nt][v];
+            vsave[((int64_t)a.perm[o] * K + row_k(r)) * a.vs_stride + c] = acc[m][nt][v];
         }
       }
   }
   if (B == nullptr) return;
-  if (K == 4 || K == 8 || K == 16) {
-    // the K rows of a vertex sit in one or more lane groups of one tile
+  if (!SP && (K == 4 || K == 8 || K == 16)) {
 #pragma unroll
     for (int m = 0; m < MTW; ++m)
 #pragma unroll
@@ -377,41 +445,37 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
         if (K >= 8) sum += __shfl_xor(sum, 16, 64);
         if (K >= 16) sum += __shfl_xor(sum, 32, 64);
         const bool leader = ((lg * 4) % K) == 0;
-        const int o = b * a.V + ((wm * MTW + m) * 16 + 4 * lg) / K;
+        const int o = b * V + ((tbase + m) * 16 + 4 * lg) / K;
         if (leader && c < a.C && o < a.N) {
           const int q = c / 3, chn = c - 3 * q;
           B[((int64_t)q * a.N + a.perm[o]) * 3 + chn] = sum;
         }
       }
-  } else {
-    // generic K: weighted rows through LDS, then sums over the K rows
-    __syncthreads();
-    float *out = reinterpret_cast<float *>(smem);  // [R][NT*16]
-    constexpr int CW = NT * 16;
+    return;
+  }
+  __syncthreads();   // every wave is done with the staged chunk
+  float *out = reinterpret_cast<float *>(smem);  // [R][CW]
 #pragma unroll
-    for (int m = 0; m < MTW; ++m)
+  for (int m = 0; m < MTW; ++m)
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int cl = nt * 16 + ln;
-        const int c = cbase + cl;
+    for (int nt = 0; nt < NT; ++nt) {
+      const int cl = nt * 16 + ln;
+      const int c = cbase + cl;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int row = (wm * MTW + m) * 16 + 4 * lg + v;
-          const int k = row % K;
-          const float gk = (c < a.C) ? gcol[(size_t)k * a.Cs + c] : 0.f;
-          out[row * CW + cl] = gk * acc[m][nt][v];
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int r = (tbase + m) * 16 + 4 * lg + v;
+        out[r * CW + cl] = (c < a.C ? gcol[(size_t)row_k(r) * a.Cs + c] : 0.f) * acc[m][nt][v];
       }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < a.V * CW; idx += nthr) {
-      const int vl = idx / CW, cl = idx % CW;
-      const int o = b * a.V + vl, c = cbase + cl;
-      if (o < a.N && c < a.C) {
-        float sum = 0.f;
-        for (int k = 0; k < K; ++k) sum += out[(vl * K + k) * CW + cl];
-        const int q = c / 3, chn = c - 3 * q;
-        B[((int64_t)q * a.N + a.perm[o]) * 3 + chn] = sum;
-      }
+    }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < V * CW; idx += nthr) {
+    const int vl = idx / CW, cl = idx % CW;
+    const int o = b * V + vl, c = cbase + cl;
+    if (o < a.N && c < a.C) {
+      float sum = 0.f;
+      for (int k = 0; k < K; ++k) sum += out[(SP ? k * V + vl : vl * K + k) * CW + cl];
+      const int q = c / 3, chn = c - 3 * q;
+      B[((int64_t)q * a.N + a.perm[o]) * 3 + chn] = sum;
     }
   }
 }
@@ -421,21 +485,30 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   const int threads = (a.R / 16 / MTW) * 64;
   a.kc = CSC;
   a.wn = 1;
-  const bool reg_epi = a.K == 4 || a.K == 8 || a.K == 16;
-  size_t stage = std::max((size_t)CSC * per_step,
-                          reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
+  // the staging buffer also holds the epilogue's weighted rows [R][NT*16]
+  // when they are summed through LDS
+  const bool reg_epi = !a.sparse && (a.K == 4 || a.K == 8 || a.K == 16);
+  size_t stage = std::max((size_t)CSC * per_step, reg_epi ? (size_t)0 : (size_t)a.R * NT * 16 * sizeof(float));
   stage = (stage + 15) / 16 * 16;
   a.uc_offset = (int)stage;
-  const size_t lds = stage + sizeof(int) * (size_t)a.max_union;
+  const size_t masks = stage + sizeof(int) * (size_t)a.max_union;
+  a.mk_offset = (int)masks;
+  const size_t lds =
+      masks + (a.sparse ? (sizeof(uint16_t) * (size_t)(a.max_union / TileKind<KIND>::KSTEP) + 15) / 16 * 16 : 0);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  // the ring's reach past the last block must stay inside the slack
+  // dense blocks: the ring's reach past the last block stays inside the slack
   const size_t step_bytes = (size_t)(a.R / 16) * 64 * TileKind<KIND>::KPL * TileKind<KIND>::VSZ;
-  if ((size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
+  if (!a.sparse && (size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
-  if (a.n_groups == 1 && a.stream_w)
-    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2>), dim3(hw), dim3(threads), lds, st, a);
+  const bool nt_w = a.n_groups == 1 && a.stream_w;
+  if (a.sparse && nt_w)
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2, true>), dim3(hw), dim3(threads), lds, st, a);
+  else if (a.sparse)
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0, true>), dim3(hw), dim3(threads), lds, st, a);
+  else if (nt_w)
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2, false>), dim3(hw), dim3(threads), lds, st, a);
   else
-    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0>), dim3(hw), dim3(threads), lds, st, a);
+    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0, false>), dim3(hw), dim3(threads), lds, st, a);
   return hipGetLastError();
 }
 

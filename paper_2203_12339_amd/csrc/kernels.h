@@ -100,9 +100,11 @@ int stream_waves(int N, int K, int waves_per_cu);
 
 // Transport on block-dense tiles (16-bit or f32 storage, f32 compute).
 struct TileArgs {
-  const int64_t *blk_off;  // [n_blocks+1] union offsets
-  const int32_t *ucol;     // union column ids
-  const void *val;         // fragment-ordered values
+  const int64_t *blk_off;  // [n_blocks+1] entry offsets (multiples of the k-step)
+  const int32_t *ucol;     // entries' column ids
+  const uint16_t *fmask;   // [entries / kstep] stored m-tiles per k-step
+  const int64_t *foff;     // [n_blocks+1] fragment offsets
+  const void *val;         // stored fragments (operand order)
   int V, K, R, n_blocks, N;
   const void *ehat;        // [n_rows][Cs] float32
   const void *ehat2;       // [n_rows][Cs] hi|lo split (16-bit kinds)
@@ -115,15 +117,17 @@ struct TileArgs {
   int max_union;           // largest union of a block (entries)
   int shape;               // 16-bit kinds, 8 m-tiles: 100 MTW + 10 NT + IPT, 0 = built-in
   int stream_w;            // 1: the tile values exceed the Infinity Cache (W streams once)
-  int wn, kc, n_groups, uc_offset;  // set by launch_tiles
+  int sparse;              // 1: fragment-sparse blocks (rows (k, o), step masks)
+  int wn, kc, n_groups, uc_offset, mk_offset;  // set by launch_tiles
 };
 hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
 // Largest block (rows V*K) the tile kernel takes for a storage type.
 int tile_max_rows(int vdt);
-// Zeroed bytes allocated after the tile values: the W register ring of the
+// Zeroed bytes allocated after dense tile values: the W register ring of the
 // last block reads up to 2*PD - 1 steps (at most 62 KB) past its end.
-// launch_tiles refuses a shape whose ring would reach further.
+// launch_tiles refuses a shape whose ring would reach further.  (Sparse
+// blocks address every fragment through the range-checked offset.)
 constexpr size_t TILE_VAL_SLACK = 128 * 1024;
 
 // Outgoing Fresnel factor (1/pi) F_t(eta, w_o) applied to B in place.
@@ -181,18 +185,22 @@ int build_sort_max();
 hipError_t launch_build_select(const BuildArgs &a, int KG, hipStream_t st);
 hipError_t launch_build_sort(const BuildArgs &a, hipStream_t st);
 
-// Block-dense tiles from the device rows (count pass, then fill pass).  A
-// block holds V consecutive Morton vertices, i.e. R = V*K rows (o, k).  Its
-// columns are the sorted union U of the kept columns of those rows, padded
-// to a multiple of `kstep` (padding columns point at column 0 with zero
-// weights).  Values are stored densely over [U x R] in operand order: for
-// k-step s, m-tile t (16 rows), lane l and element i < kpl the value
-// W[row = 16t + l%16][u = s*kstep + kpl*(l/16) + i], where kpl = kstep/4.
-// With residuals (BF16 storage, `res` non-null) the union is followed by
-// its h columns below head_cols once more (h <= head_cols: they are the
-// union's first h entries, in the same order), whose values are the BF16
-// residuals of those rows' entries, so the product adds W - bf16(W) for the
-// coarsest columns; the padding follows.
+// Fragment-sparse (`order`) or dense tiles from the device rows (count
+// pass, then fill pass).  A block holds V consecutive Morton vertices, i.e.
+// R = V*K rows, ordered (k, o) (row k*V + o - v0) when sparse, else (o, k).  Its entries are the union U of the kept
+// columns of those rows (with residuals, BF16 storage and `res` non-null,
+// the union's h columns below head_cols once more, whose values are the
+// BF16 residuals of those rows' entries, so the product adds W - bf16(W)
+// for the coarsest columns).  With `order`, the entries are sorted by the
+// first and last 16-row m-tile that keeps them (then by entry), which
+// gathers the entries kept by the same rows into the same k-steps; padded
+// to a multiple of `kstep` (padding entries read column 0 with zero
+// weights).  Per k-step s a mask of the m-tiles t with a kept entry in it;
+// only those (s, t) fragments are stored, in (s, t) order, each as the
+// matrix-instruction operand: lane l, element i < kpl = kstep/4 holds
+// W[row 16t + l%16][entry s*kstep + kpl*(l/16) + i].  Without `order` (or
+// for unions above 8192 entries) the entries stay in column order and every
+// fragment is stored (the mask of every step is full).
 struct TileBuildArgs {
   const int32_t *col;      // [N*K][n_keep] ascending
   const void *val;         // storage values (esz bytes)
@@ -201,13 +209,18 @@ struct TileBuildArgs {
   int64_t n_keep;
   int n_words;             // ceil(n_cols / 32)
   int n_blocks, kstep;
-  int64_t *count;          // count pass: padded union size per block
-  const int64_t *blk_off;  // fill pass: [n_blocks+1]
-  int32_t *ucol;
-  void *tval;              // zero-initialised
+  bool order;              // sort the entries by m-tile pattern (fits the LDS)
+  int64_t *count;          // count pass: padded entries per block
+  int64_t *fcount;         // count pass: stored fragments per block
+  const int64_t *blk_off;  // fill pass: [n_blocks+1] entry offsets
+  const int64_t *frag_off; // fill pass: [n_blocks+1] fragment offsets
+  int32_t *ucol;           // [entries]
+  uint16_t *mask;          // [entries / kstep] m-tile mask per k-step
+  void *tval;              // [fragments][64][kpl] storage values, zero-initialised
   const uint16_t *res;     // [N*K][head_cols] residuals, or nullptr
   int head_cols;           // <= 64
 };
+size_t tile_build_lds(int n_words, bool order);
 hipError_t launch_tile_count(const TileBuildArgs &a, hipStream_t st);
 hipError_t launch_tile_fill(const TileBuildArgs &a, hipStream_t st);
 

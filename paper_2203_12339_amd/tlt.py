@@ -94,6 +94,7 @@ _set_lighting = _sig("set_lighting", ctypes.c_int, _p, ctypes.c_int, _p)
 _render = _sig("render", ctypes.c_int, _p, _p, _p, ctypes.c_int)
 _render_backward = _sig("render_backward", ctypes.c_int, _p, _p, _p, _p, _p)
 _render_backward_noalloc = _sig("render_backward_noalloc", ctypes.c_int, _p, _p, _p, _p, _p)
+_tile_info = _sig("tlt_tile_info", ctypes.c_int, _p, _p, _p, _p, _p, _p, _p)
 _read_rows = _sig("tlt_read_rows", ctypes.c_int, _p, ctypes.c_int64,
                   ctypes.POINTER(ctypes.c_int64), _i32p, _f64p)
 _read_state = _sig("tlt_read_state", ctypes.c_int, _p, ctypes.c_int, _p,
@@ -127,7 +128,7 @@ _build_rows = _sig("tlt_build_rows", ctypes.c_int, ctypes.c_int32, ctypes.c_int3
 EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", "tlt_last_error", "load_transport",
             "tlt_check_transport", "tlt_material_status",
             "set_material", "set_lighting", "render", "render_backward", "render_backward_noalloc",
-            "tlt_read_rows",
+            "tlt_read_rows", "tlt_tile_info",
             "tlt_read_state", "tlt_set_tile", "tlt_get_tile", "tlt_version",
             "tlt_set_tuning", "tlt_profile_enable", "tlt_profile_read", "set_irradiance",
             "load_spatial", "tlt_spatial_info", "tlt_read_spatial", "tlt_spatial_rows",
@@ -135,13 +136,14 @@ EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", 
 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
 TUNE_SPATIAL_LANES, TUNE_SPATIAL_UNROLL, TUNE_SPATIAL_SYNTH_LANES, TUNE_SPATIAL_SEGMENT = 5, 6, 7, 8
-TUNE_TILE_SHAPE, TUNE_IRRADIANCE_HAAR, TUNE_BF16_HEAD = 9, 10, 11
+TUNE_TILE_SHAPE, TUNE_IRRADIANCE_HAAR, TUNE_BF16_HEAD, TUNE_TILE_SPARSE = 9, 10, 11, 12
 TUNING_KEYS = {"tile_chunk": TUNE_TILE_CHUNK, "stream_waves_per_cu": TUNE_STREAM_WAVES_PER_CU,
                "stream_epl": TUNE_STREAM_EPL, "stream_nt": TUNE_STREAM_NT,
                "spatial_lanes": TUNE_SPATIAL_LANES, "spatial_unroll": TUNE_SPATIAL_UNROLL,
                "spatial_synth_lanes": TUNE_SPATIAL_SYNTH_LANES,
                "spatial_segment": TUNE_SPATIAL_SEGMENT, "tile_shape": TUNE_TILE_SHAPE,
-               "irradiance_haar": TUNE_IRRADIANCE_HAAR, "bf16_head": TUNE_BF16_HEAD}
+               "irradiance_haar": TUNE_IRRADIANCE_HAAR, "bf16_head": TUNE_BF16_HEAD,
+               "tile_sparse": TUNE_TILE_SPARSE}
 
 
 class TltError(RuntimeError):
@@ -544,6 +546,15 @@ class Renderer:
         _check(_read_rows(self._h, len(rows), _ptr(rows, ctypes.c_int64),
                           _ptr(col, ctypes.c_int32), _ptr(val, ctypes.c_double)), self._h)
         return col, val
+
+    def tile_info(self):
+        """Shape of the loaded tiles (tlt_tile_info)."""
+        v, sp = ctypes.c_int32(), ctypes.c_int32()
+        nb, ne, nf, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_tile_info(self._h, ctypes.byref(v), ctypes.byref(nb), ctypes.byref(ne), ctypes.byref(nf),
+                          ctypes.byref(nbytes), ctypes.byref(sp)), self._h)
+        return {"vertices": v.value, "blocks": nb.value, "entries": ne.value, "fragments": nf.value,
+                "value_bytes": nbytes.value, "sparse": bool(sp.value)}
 
     def read_state(self, which):
         nbytes = ctypes.c_size_t()

@@ -17,11 +17,12 @@ def scene_for(w: synth.Workload, K=None):
 
 
 def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout="auto",
-                 tile_vertices=0, tuned=True, bf16_head=True) -> Renderer:
+                 tile_vertices=0, tuned=True, bf16_head=True, tile_sparse=0) -> Renderer:
     """A renderer with the workload's transport loaded.  With ``tuned`` (and
     no explicit tile size) the autotuner's recorded shape for exactly this
     workload is applied, if there is one.  ``bf16_head=False`` builds BF16
-    tiles without the residual words of the coarsest columns."""
+    tiles without the residual words of the coarsest columns; ``tile_sparse``
+    picks the tile form (0 built-in, 1 dense, 2 fragment-sparse)."""
     sc = scene_for(w, K) if scene is None else scene
     entry = None
     if tuned and tile_vertices == 0 and layout != "rows" and K is None:
@@ -32,6 +33,8 @@ def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout=
     r = Renderer(device)
     if not bf16_head:
         r.set_tuning("bf16_head", 1)
+    if tile_sparse:
+        r.set_tuning("tile_sparse", tile_sparse)
     r.load_transport(sc, w.n_keep, storage=w.storage, wavelet=w.wavelet, layout=layout,
                      tile_vertices=tile_vertices)
     if entry is not None:

@@ -539,6 +539,40 @@ def test_tile_wave_shapes_match_oracle(name, kw, rows):
     r.close()
 
 
+@pytest.mark.parametrize("name,kw,V", [("haar-f32-10242:batched", dict(subdiv=4, n_light=5, n_cfg=5), 8),
+                                       ("batch64-bf16-40962:shrunk", dict(subdiv=4, n_light=22, n_cfg=22), 16),
+                                       ("large-f16-163842:shrunk", dict(subdiv=4, n_light=4, n_cfg=1,
+                                                                       sample_rows=0), 32)],
+                         ids=["f32", "bf16", "f16-256rows"])
+def test_tile_forms_match_oracle(name, kw, V):
+    """Dense and fragment-sparse tiles (rows (o, k) and (k, o), entries in
+    column and in m-tile pattern order, every fragment or only those with a
+    kept coefficient) render the oracle's result, with the adjoint's P built
+    from them too; the sparse form stores fewer fragments."""
+    from oracle import adjoint
+    w = _workload(name, kw)
+    L = synth.make_lighting(w)
+    th = synth.make_materials(w)
+    o = oracle_scene(w)
+    ref = o.render(L, th)
+    bb = np.random.default_rng(3).standard_normal(ref.shape)
+    gL_ref, gT_ref = adjoint.grad(o, L, th, bb)
+    frags = {}
+    for form in (1, 2):
+        r = renderer_for(w, tile_vertices=V, tile_sparse=form)
+        frags[form] = r.tile_info()["fragments"]
+        _, _, _, B = _render(w, L, th, renderer=r, save=True)
+        e = normwise(B, ref)
+        say(f"[forms] {name} V={V} form={form}: {frags[form]} fragments, normwise {e:.3e}")
+        assert e <= TOL[w.storage], (form, e)
+        if w.n_cfg == 1 or w.n_light == w.n_cfg:
+            dSH, dTh = r.render_backward(dev_tensor(bb, "f32"))
+            for g, gr in ((dSH.cpu().numpy(), gL_ref), (dTh.cpu().numpy(), gT_ref)):
+                assert np.abs(g - gr).max() / np.abs(gr).max() <= TOL[w.storage], form
+        r.close()
+    assert frags[2] < frags[1], frags
+
+
 def test_autotune_sweeps_shapes_that_all_match_oracle():
     """The autotuner's sweep on a small workload, and every swept tile block
     size rendering the oracle's result."""

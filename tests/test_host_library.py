@@ -119,11 +119,14 @@ def test_autotune_candidates_and_table():
     for K in (4, 6, 8, 12, 16):
         for V in autotune.vertex_candidates(K):
             assert (V * K) % 16 == 0 and 48 <= V * K <= 128
+        for V in autotune.vertex_candidates(K, "f16"):
+            assert (V * K) % 16 == 0 and (48 <= V * K <= 128 or V * K == 256)
     assert autotune.vertex_candidates(6) == [8, 16]
+    assert autotune.vertex_candidates(8, "bf16") == [6, 8, 10, 12, 14, 16, 32]
     for key, e in autotune.load_table().items():
         storage, K = key.split("/")[0], int(key.split("/")[1][1:])
         assert storage in ("f32", "bf16", "f16")
-        assert e["tile_vertices"] in autotune.vertex_candidates(K)
+        assert e["tile_vertices"] in autotune.vertex_candidates(K, storage)
         assert e["tile_chunk"] in autotune.chunk_candidates(storage)
         assert e.get("tile_shape", 0) in autotune.shape_candidates(storage, e["tile_vertices"] * K)
         assert e["key"] == key
