@@ -502,11 +502,12 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                fragment stored); 2 = fragment-sparse
  *                                (rows (k, o), entries ordered by the rows
  *                                that keep them, fragments without a kept
- *                                coefficient left out); 0 (default) =
- *                                sparse for blocks of 256 rows of 16-bit
- *                                storage, else dense (applies at the next
- *                                load_transport; float32 summation order
- *                                only)
+ *                                coefficient left out; 16-bit storage
+ *                                only, float32 tiles stay dense); 0
+ *                                (default) = sparse for blocks of 256 rows
+ *                                of 16-bit storage, else dense (applies at
+ *                                the next load_transport; float32 summation
+ *                                order only)
  * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
  * key or a value out of range.  Results do not depend on the tuning beyond
  * float32 summation order.

@@ -2,10 +2,11 @@
 
 For one workload it sweeps, on the GPU at hand, the tile block size (the
 vertices whose rows share one column union, which fixes both the bytes
-streamed per kept coefficient and the operand reuse), the number of
-k-steps whose irradiance rows the tile kernel stages at once and, for
-16-bit blocks of 128 rows, the wave shape (m-tiles and column tiles per
-wave).  Each shape is
+streamed per kept coefficient and the operand reuse), for 16-bit blocks
+of 128 and 256 rows the tile form (dense, or only the fragments holding a
+kept coefficient) and the wave shape (m-tiles and column tiles per wave),
+and the number of k-steps whose irradiance rows the tile kernel stages at
+once.  Each shape is
 timed with the library's own stage timing (transport kernel only, every
 stage recomputed), and the fastest is recorded in a table keyed by what
 fixes the kernel's shape: storage type, PCA terms, output columns, vertex
@@ -58,6 +59,15 @@ def shape_candidates(storage: str, rows: int) -> list:
     return [0, 241, 432] if rows == 128 else [0, 241] if rows == 256 else [0]
 
 
+def form_candidates(storage: str, rows: int) -> list:
+    """Tile forms (0 = built-in, 1 = dense, 2 = fragment-sparse): 16-bit
+    blocks of 128 rows are dense by default, those of 256 rows sparse; both
+    sizes also try the other form."""
+    if storage == "f32" or rows not in (128, 256):
+        return [0]
+    return [0, 2] if rows == 128 else [0, 1]
+
+
 def load_table(path: str = TABLE) -> dict:
     if not os.path.exists(path):
         return {}
@@ -103,28 +113,32 @@ def tune(w, device: int = 0, steps: int = 64, log=print) -> dict:
     th = torch.tensor(synth.make_materials(w), dtype=torch.float64, device=dev)
     B = torch.empty((w.n_out, w.n_vertices, 3), dtype=torch.float32, device=dev)
     results = []
+    forms = ("built-in", "dense", "sparse")
     for V in vertex_candidates(w.K, w.storage):
-        r = Renderer(device)
-        try:
-            r.load_transport(scene, w.n_keep, storage=w.storage, wavelet=w.wavelet,
-                             layout="tiles", tile_vertices=V)
-            r.set_lighting(L)
-            r.set_material(th)
-            for shape in shape_candidates(w.storage, V * w.K):
-                r.set_tuning("tile_shape", shape)
-                for kc in chunk_candidates(w.storage):
-                    r.set_tuning("tile_chunk", kc)
-                    us = _time_transport(r, B, steps)
-                    results.append({"tile_vertices": V, "tile_chunk": kc, "tile_shape": shape,
-                                    "transport_us": round(us, 2)})
-                    log(f"[autotune] {w.name}: V={V} shape={shape or 'built-in'} "
-                        f"chunk={kc or 'max'}: {us:.1f} us")
-        finally:
-            r.close()
+        for form in form_candidates(w.storage, V * w.K):
+            r = Renderer(device)
+            try:
+                if form:
+                    r.set_tuning("tile_sparse", form)
+                r.load_transport(scene, w.n_keep, storage=w.storage, wavelet=w.wavelet,
+                                 layout="tiles", tile_vertices=V)
+                r.set_lighting(L)
+                r.set_material(th)
+                for shape in shape_candidates(w.storage, V * w.K):
+                    r.set_tuning("tile_shape", shape)
+                    for kc in chunk_candidates(w.storage):
+                        r.set_tuning("tile_chunk", kc)
+                        us = _time_transport(r, B, steps)
+                        results.append({"tile_vertices": V, "tile_sparse": form, "tile_chunk": kc,
+                                        "tile_shape": shape, "transport_us": round(us, 2)})
+                        log(f"[autotune] {w.name}: V={V} form={forms[form]} "
+                            f"shape={shape or 'built-in'} chunk={kc or 'max'}: {us:.1f} us")
+            finally:
+                r.close()
     best = min(results, key=lambda e: e["transport_us"])
     return {"key": workload_key(w), "workload": w.name, "tile_vertices": best["tile_vertices"],
-            "tile_chunk": best["tile_chunk"], "tile_shape": best["tile_shape"],
-            "transport_us": best["transport_us"],
+            "tile_sparse": best["tile_sparse"], "tile_chunk": best["tile_chunk"],
+            "tile_shape": best["tile_shape"], "transport_us": best["transport_us"],
             "device": torch.cuda.get_device_name(device), "steps": steps,
             "tuned": time.strftime("%Y-%m-%d"), "sweep": results}
 
@@ -145,8 +159,8 @@ def main(argv=None) -> int:
         e = tune(synth.get(name), steps=args.steps,
                  log=lambda *a: print(*a, file=sys.stderr, flush=True))
         table[e["key"]] = e
-        print(json.dumps({k: e[k] for k in ("key", "tile_vertices", "tile_chunk", "tile_shape",
-                                            "transport_us")}),
+        print(json.dumps({k: e[k] for k in ("key", "tile_vertices", "tile_sparse", "tile_chunk",
+                                            "tile_shape", "transport_us")}),
               flush=True)
     if args.write:
         with open(args.write, "w") as fh:

@@ -810,8 +810,8 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   // bound by their matrix work, which the sparse form cannot shorten (a
   // workgroup's waves wait for the fullest one at every staged chunk)
   {
-    const bool want = c->tune_tile_sparse == 2 ||
-                      (c->tune_tile_sparse == 0 && c->vdt != TLT_F32 && tV * c->K == 256);
+    const bool want = c->vdt != TLT_F32 &&
+                      (c->tune_tile_sparse == 2 || (c->tune_tile_sparse == 0 && tV * c->K == 256));
     a.order = want && tile_build_lds(a.n_words, true) <= (size_t)150 * 1024;
   }
   int64_t *cnt = nullptr, *fcnt = nullptr;

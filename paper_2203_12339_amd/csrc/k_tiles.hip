@@ -138,8 +138,11 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   const int b = (blockIdx.x & 7) * per_xcd + slot / ng;
   const int grp = slot % ng;
   if (slot / ng >= per_xcd || b >= a.n_blocks) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = wave;  // waves split the m-tiles
+  const int lane = threadIdx.x & 63;
+  // waves split the m-tiles; the sparse form branches on the wave's m-tiles,
+  // so its wave index is made a scalar
+  const int wave = SP ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
+  const int wm = wave;
   const int nthr = blockDim.x;
   const int cbase = grp * NT * 16;
   const int cg = min(NT * 16, a.C - cbase);  // real columns of this group
@@ -253,7 +256,10 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   // absent fragment (and every step past the block's end, whose mask reads
   // as 0) gets an offset past the range, which the buffer bound turns into
   // zeros without a memory access.  All offsets are in the vector operand,
-  // which the range check covers.
+  // which the range check covers.  The masks of the 64 steps from the
+  // current chunk's first one sit one per lane in a register (cm) and are
+  // taken out with a scalar lane read: the frontier of chunk step sl is
+  // step sl + PD < 64 of the window (16-bit chunks hold at most 16 steps).
   constexpr int FRAG = 64 * KPL * TK::VSZ;   // bytes per stored fragment
   constexpr int OOB = 0x7ffff000;
   const __amdgpu_buffer_rsrc_t wrs = __builtin_amdgcn_make_buffer_rsrc(
@@ -263,12 +269,14 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   uint32_t fp_load = 0;
   int s_load = 0;
   const int MT = a.R / 16;
-  auto step_mask = [&](int s) -> uint32_t {
-    return __builtin_amdgcn_readfirstlane(s < n_steps ? (uint32_t)mk[s] : 0u);
+  uint32_t cm = 0;
+  auto mask_window = [&](int s0) {
+    if constexpr (SP) cm = s0 + lane < n_steps ? (uint32_t)mk[s0 + lane] : 0u;
   };
-  auto load_next = [&](AFrag (&dst)[MTW]) {
+  auto win = [&](int i) -> uint32_t { return (uint32_t)__builtin_amdgcn_readlane((int)cm, i); };
+  // ms: the mask of the frontier step (sparse form only)
+  auto load_next = [&](AFrag (&dst)[MTW], uint32_t ms) {
     if constexpr (SP) {
-      const uint32_t ms = step_mask(s_load);
 #pragma unroll
       for (int m = 0; m < MTW; ++m) {
         const int t = tbase + m;
@@ -314,9 +322,13 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       }
   };
   AFrag ring[PD][MTW];
-  if constexpr (SP) __syncthreads();  // step masks visible
+  if constexpr (SP) {
+    static_assert(!SP || KIND != 0, "fragment-sparse tiles are 16-bit");
+    __syncthreads();  // step masks visible
+  }
+  mask_window(0);
 #pragma unroll
-  for (int p = 0; p < PD; ++p) load_next(ring[p]);
+  for (int p = 0; p < PD; ++p) load_next(ring[p], SP ? win(p) : 0u);
 
   int ns = min(CS, n_steps);
   gather(0, ns);
@@ -326,6 +338,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     const int nxt = s0 + CS;
     const int ns_next = min(CS, n_steps - nxt);
     if (ns_next > 0) gather(nxt, ns_next);
+    if (s0 > 0) mask_window(s0);
     // Groups of PD steps: a group runs whole or not at all, so the W ring
     // stays in step (one refill per step, in step order) and the load
     // counters can be waited on exactly.  A step whose mask has none of the
@@ -348,20 +361,28 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
         for (int p = 0; p < PD; ++p) {
           const int sl = g0 + p;
           if constexpr (SP) {
-            const uint32_t wb = (step_mask(s0 + sl) >> tbase) & ((1u << MTW) - 1u);
+            // scalar: this wave's m-tiles stored at this step
+            const uint32_t wb = (win(sl) >> tbase) & ((1u << MTW) - 1u);
             if (wb != 0u) {   // then sl < ns
               BFrag bf[NT][H];
-              if constexpr (KIND == 0)
-                bf[0][0] = bg[p];
-              else
-                read_b(sl, bf);
+              read_b(sl, bf);
+              if (wb == (1u << MTW) - 1u) {
 #pragma unroll
-              for (int nt = 0; nt < NT; ++nt)
+                for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int h = 0; h < H; ++h)
+                  for (int h = 0; h < H; ++h)
 #pragma unroll
-                  for (int m = 0; m < MTW; ++m)
-                    if ((wb >> m) & 1u) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
+                    for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
+              } else {
+#pragma unroll
+                for (int m = 0; m < MTW; ++m)
+                  if ((wb >> m) & 1u) {
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                      for (int h = 0; h < H; ++h) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
+                  }
+              }
             }
           } else {
             // dense: steps of the last group past the chunk's end multiply
@@ -385,7 +406,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
 #pragma unroll
                 for (int m = 0; m < MTW; ++m) acc[m][nt] = TK::mma(ring[p][m], bf[nt][h], acc[m][nt]);
           }
-          load_next(ring[p]);  // refill this slot PD steps ahead
+          load_next(ring[p], SP ? win(sl + PD) : 0u);  // refill this slot PD steps ahead
           // keep the refill right behind its step (no regrouping of loads)
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -501,11 +522,21 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   if (!a.sparse && (size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
   const bool nt_w = a.n_groups == 1 && a.stream_w;
-  if (a.sparse && nt_w)
-    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2, true>), dim3(hw), dim3(threads), lds, st, a);
-  else if (a.sparse)
-    TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0, true>), dim3(hw), dim3(threads), lds, st, a);
-  else if (nt_w)
+  if constexpr (KIND == 0) {
+    if (a.sparse) return hipErrorInvalidValue;   // fragment-sparse tiles are 16-bit
+  } else {
+    // the mask window covers the ring's reach: CSC - 1 + PD < 64
+    static_assert(CSC + PD <= 64, "mask window");
+    if (a.sparse && nt_w) {
+      TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2, true>), dim3(hw), dim3(threads), lds, st, a);
+      return hipGetLastError();
+    }
+    if (a.sparse) {
+      TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0, true>), dim3(hw), dim3(threads), lds, st, a);
+      return hipGetLastError();
+    }
+  }
+  if (nt_w)
     TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 2, false>), dim3(hw), dim3(threads), lds, st, a);
   else
     TLT_LAUNCH((k_tiles<KIND, MTW, NT, PD, IPT, CGS, CSC, 0, false>), dim3(hw), dim3(threads), lds, st, a);

@@ -30,6 +30,7 @@ def renderer_for(w: synth.Workload, device: int = 0, scene=None, K=None, layout=
         entry = lookup(w)
         if entry is not None:
             tile_vertices = entry["tile_vertices"]
+            tile_sparse = tile_sparse or entry.get("tile_sparse", 0)
     r = Renderer(device)
     if not bf16_head:
         r.set_tuning("bf16_head", 1)

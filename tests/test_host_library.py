@@ -129,7 +129,10 @@ def test_autotune_candidates_and_table():
         assert e["tile_vertices"] in autotune.vertex_candidates(K, storage)
         assert e["tile_chunk"] in autotune.chunk_candidates(storage)
         assert e.get("tile_shape", 0) in autotune.shape_candidates(storage, e["tile_vertices"] * K)
+        assert e.get("tile_sparse", 0) in autotune.form_candidates(storage, e["tile_vertices"] * K)
         assert e["key"] == key
+    assert autotune.form_candidates("f16", 256) == [0, 1] and autotune.form_candidates("bf16", 128) == [0, 2]
+    assert autotune.form_candidates("f32", 128) == [0] and autotune.form_candidates("f16", 112) == [0]
     assert autotune.shape_candidates("bf16", 128) == [0, 241, 432]
     assert autotune.shape_candidates("f32", 128) == [0] and autotune.shape_candidates("f16", 112) == [0]
 
