@@ -555,7 +555,16 @@ static hipError_t tiles_go(TileArgs a, int nt_total, hipStream_t st) {
   if (KIND == 0 && cmax > CGS) return hipErrorInvalidValue;
   const size_t per_step = KIND == 0 ? (size_t)4 * CGS * sizeof(float)
                                     : (size_t)NT * TK::H * 64 * TK::KPL * sizeof(typename TK::BElem);
-  int cs = std::min<int>((int)(TILE_LDS / per_step), IPT * threads / items_per_step);
+  // staging budget: TILE_LDS, or for blocks of 16 m-tiles -- one
+  // workgroup of eight waves per CU at their register count -- what the
+  // CU's LDS leaves beside the union ids and step masks
+  size_t budget = TILE_LDS;
+  if (MT == 16) {
+    const size_t fixed = sizeof(int) * (size_t)a.max_union +
+                         sizeof(uint16_t) * (size_t)(a.max_union / TK::KSTEP) + 64;
+    budget = fixed < (size_t)160 * 1024 ? (size_t)160 * 1024 - fixed : 0;
+  }
+  int cs = std::min<int>((int)(budget / per_step), IPT * threads / items_per_step);
   if (a.kc > 0) cs = std::min(cs, a.kc);  // caller override (tuning)
   if (cs < PD || (size_t)PD * items_per_step > (size_t)IPT * threads) return hipErrorInvalidValue;
   a.n_groups = (nt_total + NT - 1) / NT;
@@ -593,10 +602,13 @@ static hipError_t tiles_kind(const TileArgs &a, hipStream_t st) {
       // 256-row blocks (16-bit storage): eight waves of two m-tiles share
       // each staged irradiance row, so the gathered bytes per W byte halve
       // against 128-row blocks
+      // With three or four column tiles, chunks of 16 steps (the default,
+      // or a chunk cap of 16) take two gathered items per thread.
       if (ntw == 1) return tiles_go<KIND, 2, 1, 4, 1>(a, nt, st);
       if (ntw == 2) return tiles_go<KIND, 2, 2, 4, 1>(a, nt, st);
-      if (a.shape == 241) return tiles_go<KIND, 2, 4, 4, 1>(a, nt, st);
-      return tiles_go<KIND, 2, 3, 4, 1>(a, nt, st);
+      const bool two = a.kc == 0 || a.kc >= 16;
+      if (a.shape == 241) return two ? tiles_go<KIND, 2, 4, 4, 2>(a, nt, st) : tiles_go<KIND, 2, 4, 4, 1>(a, nt, st);
+      return two ? tiles_go<KIND, 2, 3, 4, 2>(a, nt, st) : tiles_go<KIND, 2, 3, 4, 1>(a, nt, st);
     }
     if (MT == 8) {
       // tuned shapes: more m-tiles per wave halve the LDS reads of the
