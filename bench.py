@@ -356,6 +356,13 @@ def main():
     if args.tile:
         r.set_tile(args.tile)
     log(f"[bench] precompute + load {time.perf_counter() - t0:.1f}s")
+    try:
+        ti = r.tile_info()
+        log(f"[bench] tiles: {ti['vertices']} vertices per block, {ti['blocks']} blocks, "
+            f"{ti['entries']} entries, {ti['fragments']} fragments "
+            f"({'sparse' if ti['sparse'] else 'dense'}), {ti['value_bytes']} value bytes")
+    except tlt.TltError:
+        pass   # no tiles loaded (rows layout)
     sp = None
     if args.spatial:
         t0 = time.perf_counter()
@@ -510,6 +517,15 @@ def main():
                                                 "probe, over 1 GiB on this GPU"}
     if cold is not None:
         roofline["cold"] = cold
+    if traffic:
+        # the tiles store fewer bytes than the algorithmic count (no index per
+        # kept coefficient, and no fragment without a kept one), so the
+        # measured HBM bytes over the same kernel time say how well it streams
+        phys = traffic / (prim["kernel_us"] * 1e-6) / 1e9
+        roofline["physical"] = {"GBps": round(phys, 1), "frac": round(phys / HBM_PEAK_GBS, 4),
+                                "basis": "traffic / kernel_us"}
+        if copy_gbs:
+            roofline["physical"]["frac_of_read_probe"] = round(phys / copy_gbs[2], 4)
     roofline_adj = None
     if args.backward and stage_ms["adjoint"][1] > 0:
         # the lighting-transfer product P read once and the upstream
