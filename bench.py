@@ -477,9 +477,11 @@ def main():
         kernel, traffic = "k_combine", None
         flops = 2.0 * w.K * w.n_vertices * C
     elif args.folded:
-        # P_k rows read once (Psh >= n_sh columns, as stored), B written once
+        # P_k rows read once (Psh >= n_sh columns, as stored: an FP16 copy
+        # with 16-bit storage), B written once
         psh = next(v for v in (4, 8, 12, 16, 24, 28, 32, 36, 48, 64) if v >= w.n_sh)
-        alg_bytes = w.K * w.n_vertices * psh * esz + w.n_vertices * C * esz
+        psz = 2 if w.storage in ("f16", "bf16") else esz
+        alg_bytes = w.K * w.n_vertices * psh * psz + w.n_vertices * C * esz
         kernel, traffic = "k_folded", None
         flops = 2.0 * w.K * w.n_vertices * w.n_sh * C
     else:

@@ -302,8 +302,11 @@ tlt_status set_view(tlt_ctx *ctx, const double *eye, const double *position, con
  * TLT_FOLDED_LIGHTING renders through the lighting transport folded at load,
  * P_k = W_k H (A o T) (the SH-lighting path of Eq. 14): B = sum_k g_k P_k L,
  * equal to the wavelet transport of the same kept coefficients up to
- * float32 rounding, reading K*N*Psh values instead of the transport
- * (incompatible with TLT_KEEP_TERMS and TLT_PLAIN_ROWS: TLT_E_ARG).
+ * rounding, reading K*N*Psh values instead of the transport (incompatible
+ * with TLT_KEEP_TERMS and TLT_PLAIN_ROWS: TLT_E_ARG).  With 16-bit
+ * storage the product reads an FP16 copy of P (built at the first folded
+ * render, scaled by a power of two; ~2.4e-4 relative rounding per value,
+ * the weighted lighting split hi + lo) unless TLT_TUNE_FOLDED_FP32.
  * TLT_SPATIAL renders through the spatially compressed transport of
  * load_spatial (Eq. 10, Steps 2, 4 and 5 of Sec. 4), recomputing every stage;
  * TLT_E_STATE without load_spatial, TLT_E_ARG combined with
@@ -508,6 +511,9 @@ int tlt_get_tile(const tlt_ctx *ctx);
  *                                of 16-bit storage, else dense (applies at
  *                                the next load_transport; float32 summation
  *                                order only)
+ *   TLT_TUNE_FOLDED_FP32         1 = folded lighting reads the float32 P
+ *                                also with 16-bit storage (default 0: its
+ *                                FP16 copy, half the bytes)
  * Values are clamped to what a launch supports.  TLT_E_ARG for an unknown
  * key or a value out of range.  Results do not depend on the tuning beyond
  * float32 summation order.
@@ -524,7 +530,8 @@ enum {
   TLT_TUNE_TILE_SHAPE = 9,
   TLT_TUNE_IRRADIANCE_HAAR = 10,
   TLT_TUNE_BF16_HEAD = 11,
-  TLT_TUNE_TILE_SPARSE = 12
+  TLT_TUNE_TILE_SPARSE = 12,
+  TLT_TUNE_FOLDED_FP32 = 13
 };
 tlt_status tlt_set_tuning(tlt_ctx *ctx, int32_t key, int32_t value);
 

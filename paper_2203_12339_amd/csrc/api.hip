@@ -79,6 +79,11 @@ struct tlt_ctx {
   bool have_P = false;
   int Psh = 0, Gs = 0;
   void *P = nullptr;
+  // FP16 copy of P (16-bit storage, folded lighting; built at the first
+  // folded render): sp P in matrix fragment order, p16_inv = 1 / sp
+  void *P16 = nullptr;
+  float p16_inv = 0.f;
+  int tune_fold_fp32 = 0;   // 1: folded lighting on the float32 P
 
   // view for the outgoing Fresnel factor (set_view): cos(w_o, n) per
   // Morton position, compute precision
@@ -266,6 +271,8 @@ void free_all(tlt_ctx *c) {
   dfree(c->rn);
   dfree(c->basis);
   dfree(c->P);
+  dfree(c->P16);
+  c->p16_inv = 0.f;
   dfree(c->zero_v);
   c->n_zero = 0;
   c->n_waves = 0;   // the partition belongs to the freed transport
@@ -538,6 +545,43 @@ out:
   dfree(part);
   dfree(gz);
   return s;
+}
+
+// The FP16 copy of P for the folded product (16-bit storage): scale sp puts
+// the largest |P| in [2^13, 2^14).  A P that is not finite keeps the float32
+// product (TLT_E_STATE otherwise would block a render the float32 form can
+// do).
+tlt_status ensure_P16(tlt_ctx *c, hipStream_t st) {
+  if (c->P16 || c->vdt == TLT_F32 || c->fp64) return TLT_OK;
+  const int J = c->K * c->Psh;
+  if ((J + 31) / 32 > FOLD16_MAX_STEPS) return TLT_OK;
+  unsigned *mx = nullptr;
+  tlt_status s;
+  if ((s = dalloc(c, (void **)&mx, sizeof(unsigned), "P maximum")) != TLT_OK) return s;
+  unsigned bits = 0;
+  hipError_t he;
+  if ((he = hipMemset(mx, 0, sizeof(unsigned))) != hipSuccess ||
+      (he = launch_fold_absmax((const float *)c->P, (int64_t)c->N * J, mx, st)) != hipSuccess ||
+      (he = hipMemcpyAsync(&bits, mx, sizeof(unsigned), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess) {
+    dfree(mx);
+    return hip_fail(c, he, "P maximum");
+  }
+  dfree(mx);
+  float pmax;
+  std::memcpy(&pmax, &bits, sizeof(pmax));
+  if (!std::isfinite(pmax)) return TLT_OK;
+  int e = 0;
+  (void)std::frexp(pmax, &e);
+  const float sp = pmax > 0.f ? std::ldexp(1.f, 14 - e) : 1.f;
+  if ((s = dalloc(c, &c->P16, fold16_bytes(c->N, J), "P (FP16)")) != TLT_OK) return s;
+  if ((he = launch_fold_pack((const float *)c->P, c->N, J, sp, c->P16, st)) != hipSuccess ||
+      (he = hipStreamSynchronize(st)) != hipSuccess) {
+    dfree(c->P16);
+    return hip_fail(c, he, "P (FP16)");
+  }
+  c->p16_inv = 1.f / sp;
+  return TLT_OK;
 }
 
 // Stage timer: hands an event pair to the launches of one stage (written by
@@ -1355,6 +1399,7 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
   if (flags & TLT_FOLDED_LIGHTING) {
     // g_k when the material changed, then the folded product
     if (!c->have_P && (s = ensure_P(c, st)) != TLT_OK) return s;
+    if (!c->tune_fold_fp32 && (s = ensure_P16(c, st)) != TLT_OK) return s;
     if (do_gk) {
       StageTimer t(c, 0, st);
       HIPC(c, launch_prep(a, st));
@@ -1367,8 +1412,9 @@ tlt_status render(tlt_ctx *c, void *B, void *stream, int flags) {
       c->fold_bytes = need;
     }
     StageTimer t(c, 2, st);
+    const bool p16 = c->P16 && !c->tune_fold_fp32;
     HIPC(c, launch_folded(c->P, c->Psh, c->n_sh, c->K, c->gcol, c->Cs, c->sh, cols, c->N, B, c->fp64,
-                          c->fold, st));
+                          c->fold, st, p16 ? c->P16 : nullptr, c->p16_inv));
     c->v_valid = false;
   } else if (!relight && c->V && !spatial) {
     // material-only edit: reuse the per-term transport v_k kept by the last
@@ -1543,6 +1589,10 @@ tlt_status tlt_set_tuning(tlt_ctx *c, int32_t key, int32_t value) {
     case TLT_TUNE_TILE_SPARSE:
       if (value > 2) return fail(&c->err, TLT_E_ARG, "tile form must be 0, 1 or 2");
       c->tune_tile_sparse = value;
+      break;
+    case TLT_TUNE_FOLDED_FP32:
+      if (value > 1) return fail(&c->err, TLT_E_ARG, "folded precision flag must be 0 or 1");
+      c->tune_fold_fp32 = value;
       break;
     case TLT_TUNE_IRRADIANCE_HAAR:
       if (value > 1) return fail(&c->err, TLT_E_ARG, "irradiance flag must be 0 or 1");

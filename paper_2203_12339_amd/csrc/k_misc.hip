@@ -470,19 +470,288 @@ static hipError_t folded_go(int C, int Cs, dim3 gx, int tiles, hipStream_t st, c
   }
 }
 
+static size_t fold16_scratch(int K, int Psh, int Cs);
+
 size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64) {
-  return (size_t)K * Psh * Cs * (fp64 ? 8 : 4);
+  const size_t lg = (size_t)K * Psh * Cs * (fp64 ? 8 : 4);
+  return fp64 ? lg : std::max(lg, fold16_scratch(K, Psh, Cs));
+}
+
+// ---------------------------------------------------------------------------
+// Folded lighting on an FP16 copy of P (16-bit transport storage).  At load
+// P [N][K][Psh] (float32) is scaled by a power of two sp, which puts its
+// largest magnitude in [2^13, 2^14), and written in the A-operand fragment
+// order of v_mfma_f32_16x16x32_f16: fragment (16-row tile t, step s) holds
+// for lane l the eight values P[16 t + l % 16][32 s + 8 (l / 16) + i],
+// i = 0..7, over the contraction index j = k Psh + lm (zero past N and past
+// J = K Psh), so a wave reads one contiguous 1 KB per step.  Per frame the
+// weighted lighting Lg[(k, lm)][c] = g_k[c] L[lm][c] is written once as
+// B-operand fragments per 64-column group (k_fold_lg16, straight from g_k
+// and L): each column scaled by a power of two (from a bound on its largest
+// magnitude, so nothing exceeds the FP16 range) and split into FP16 hi + lo,
+// so Lg keeps about 22 significant bits; each workgroup copies its group's
+// fragments into LDS.  B = P Lg then runs on
+// the FP16 matrix instructions with float32 accumulation, and the epilogue
+// undoes both scales (exactly: powers of two).  The P stream is half of the
+// float32 form's and the matrix work a small fraction of its time.
+// ---------------------------------------------------------------------------
+
+typedef _Float16 h16x8 __attribute__((ext_vector_type(8)));
+
+// Largest |P| as float bits (non-negative floats order as unsigned ints;
+// a value that is not finite reports +inf).
+__global__ __launch_bounds__(256) void k_fold_absmax(const float *__restrict__ P, int64_t n,
+                                                     unsigned *__restrict__ out) {
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float v = fabsf(P[i]);
+    m = (v <= 3.0e38f) ? fmaxf(m, v) : __builtin_inff();
+  }
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+// One lane slot (16 bytes) of the FP16 copy per thread.
+__global__ __launch_bounds__(256) void k_fold_pack(const float *__restrict__ P, int N, int J, int S,
+                                                   float sp, h16x8 *__restrict__ P16) {
+  const int64_t f = blockIdx.x * 256LL + threadIdx.x;
+  if (f >= (int64_t)((N + 15) / 16) * S * 64) return;
+  const int l = (int)(f & 63);
+  const int64_t ts = f >> 6;
+  const int s = (int)(ts % S);
+  const int64_t o = (ts / S) * 16 + (l & 15);
+  const int j0 = 32 * s + 8 * (l >> 4);
+  h16x8 v;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int j = j0 + i;
+    v[i] = (o < N && j < J) ? (_Float16)(P[o * J + j] * sp) : (_Float16)0.f;
+  }
+  P16[f] = v;
+}
+
+constexpr int F16_WPB = 8;   // waves per workgroup (one 16-row tile each per round)
+
+// Weighted lighting as FP16 B-operand fragments, per 64-column group y:
+// lgf[y][s][nt][h][l] holds for lane slot l the eight values
+// Lg[32 s + 8 (l / 16) + i][c] (c = 64 y + 16 nt + l % 16, Lg[(k, lm)][c] =
+// g_k[c] L[light(c)][lm][ch(c)]) times the column scale csc[c], split hi
+// (h = 0) and lo (h = 1).  csc[c] is the power of two that puts the bound
+// max_k |g_k[c]| max_lm |L[light(c)][lm][ch(c)]| in [2^13, 2^14), so no
+// scaled value exceeds the FP16 range.  One thread per lane slot.
+__global__ __launch_bounds__(256) void k_fold_lg16(const float *__restrict__ gcol, int Cs,
+                                                   const float *__restrict__ sh, Cols cols, int K,
+                                                   int Psh, int n_sh, int S, int NTN, int gy,
+                                                   h16x8 *__restrict__ lgf, float *__restrict__ cscg) {
+  const int f = blockIdx.x * 256 + threadIdx.x;
+  const int per_group = S * NTN * 64;
+  if (f >= gy * per_group) return;
+  const int y = f / per_group, r = f - y * per_group;
+  const int l = r & 63, snt = r >> 6;
+  const int cl = (snt % NTN) * 16 + (l & 15), c = y * 64 + cl;
+  const int j0 = 32 * (snt / NTN) + 8 * (l >> 4);
+  const int J = K * Psh;
+  float sc = 1.f;
+  float v[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = 0.f;
+  if (c < cols.C) {
+    const int q = c / 3, ch = c - 3 * q;
+    const float *L = sh + (size_t)(cols.n_light > 1 ? q : 0) * n_sh * 3 + ch;
+    float mg = 0.f, mL = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < K; ++k) mg = fmaxf(mg, fabsf(gcol[(size_t)k * Cs + c]));
+#pragma unroll 12
+    for (int lm = 0; lm < n_sh; ++lm) mL = fmaxf(mL, fabsf(L[lm * 3]));
+    const float bound = mg * mL;
+    int e = 0;
+    (void)frexpf(bound, &e);
+    sc = bound > 0.f ? ldexpf(1.f, 14 - e) : 1.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int j = j0 + i, k = j / Psh, lm = j - k * Psh;
+      if (j < J && lm < n_sh) v[i] = gcol[(size_t)k * Cs + c] * L[lm * 3] * sc;
+    }
+  }
+  h16x8 hi, lo;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const _Float16 h = (_Float16)v[i];
+    hi[i] = h;
+    lo[i] = (_Float16)(v[i] - (float)h);
+  }
+  lgf[(size_t)(y * S * NTN + snt) * 128 + l] = hi;
+  lgf[(size_t)(y * S * NTN + snt) * 128 + 64 + l] = lo;
+  if (snt < NTN && l < 16) cscg[y * 64 + cl] = sc;   // step 0, lane group 0: one thread per column
+}
+
+// S steps of 32 contraction indices, NTN real 16-column tiles of the group.
+// Workgroups stay resident (two per compute unit) and take rounds of
+// F16_WPB tiles in turn; a wave requests the fragments of its next tile
+// before the matrix work of the current one (clamped to the last tile, so
+// the requests carry no branch).
+template <int S, int NTN>
+__global__ __launch_bounds__(F16_WPB * 64) __attribute__((amdgpu_waves_per_eu(S <= 9 ? 4 : 1))) void k_folded16(
+    const h16x8 *__restrict__ P16, const h16x8 *__restrict__ lgf, const float *__restrict__ cscg, int C,
+    int N, float inv_sp, float *__restrict__ B) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  h16x8 *lf = reinterpret_cast<h16x8 *>(smem);                            // [S][NTN][2][64]
+  float *csc = reinterpret_cast<float *>(smem + (size_t)S * NTN * 2 * 64 * 16);  // [64]
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+  const int cg0 = blockIdx.y * FOLD_CG;
+  const int tiles = (N + 15) / 16;
+  const int n_rounds = (tiles + F16_WPB - 1) / F16_WPB;
+  const int G = gridDim.x;
+  auto load = [&](int rb, h16x8 (&dst)[S]) {
+    const int tile = min(rb * F16_WPB + wave, tiles - 1);
+    const h16x8 *src = P16 + (int64_t)tile * S * 64 + lane;
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = src[s * 64];
+  };
+  // the first tile's fragments are requested before the staging
+  h16x8 a0[S], a1[S];
+  load(blockIdx.x, a0);
+  // the group's lighting fragments and column scales (k_fold_lg16) into LDS:
+  // every load issued before the stores
+  {
+    constexpr int NSL = S * NTN * 2 * 64, PER = (NSL + F16_WPB * 64 - 1) / (F16_WPB * 64);
+    const h16x8 *src = lgf + (size_t)blockIdx.y * NSL;
+    h16x8 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) v[u] = src[min(u * F16_WPB * 64 + t, NSL - 1)];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (u * F16_WPB * 64 + t < NSL) lf[u * F16_WPB * 64 + t] = v[u];
+    if (t < 64) csc[t] = cscg[blockIdx.y * 64 + t];
+  }
+  __syncthreads();
+  float inv_c[NTN];
+#pragma unroll
+  for (int nt = 0; nt < NTN; ++nt) inv_c[nt] = inv_sp / csc[nt * 16 + (lane & 15)];
+  auto compute = [&](int rb, const h16x8 (&a)[S]) {
+    // the staged fragments are the same for every tile: without this fence
+    // the compiler keeps all of them in registers (S NTN 8 VGPRs) instead of
+    // reading each from LDS next to its matrix instruction
+    __asm__ volatile("" ::: "memory");
+    f32x4 acc[NTN];
+#pragma unroll
+    for (int nt = 0; nt < NTN; ++nt) acc[nt] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[s], lf[((s * NTN + nt) * 2 + h) * 64 + lane],
+                                                            acc[nt], 0, 0, 0);
+    const int tile = rb * F16_WPB + wave;
+#pragma unroll
+    for (int nt = 0; nt < NTN; ++nt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = tile * 16 + 4 * (lane >> 4) + v;
+        const int c = cg0 + nt * 16 + (lane & 15);
+        if (o < N && c < C) {
+          const int q = c / 3, ch = c - 3 * q;
+          B[((int64_t)q * N + o) * 3 + ch] = acc[nt][v] * inv_c[nt];
+        }
+      }
+  };
+  for (int rb = blockIdx.x; rb < n_rounds; rb += 2 * G) {
+    load(rb + G, a1);
+    compute(rb, a0);
+    if (rb + G >= n_rounds) break;
+    load(rb + 2 * G, a0);
+    compute(rb + G, a1);
+  }
+}
+
+size_t fold16_bytes(int N, int J) {
+  const int S = (J + 31) / 32;
+  return (size_t)((N + 15) / 16) * S * 64 * 16;
+}
+
+hipError_t launch_fold_absmax(const float *P, int64_t n, unsigned *absmax, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  TLT_LAUNCH(k_fold_absmax, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, P, n, absmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold_pack(const float *P, int N, int J, float sp, void *P16, hipStream_t st) {
+  const int S = (J + 31) / 32;
+  if (S < 1 || S > FOLD16_MAX_STEPS) return hipErrorInvalidValue;
+  const int64_t slots = (int64_t)((N + 15) / 16) * S * 64;
+  TLT_LAUNCH(k_fold_pack, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, st, P, N, J, S, sp,
+             (h16x8 *)P16);
+  return hipGetLastError();
+}
+
+template <int S, int NTN>
+static hipError_t folded16_go(const void *P16, const h16x8 *lgf, const float *cscg, int Cs, int C,
+                              int N, float inv_sp, float *B, hipStream_t st) {
+  const size_t lds = (size_t)S * NTN * 2 * 64 * 16 + 64 * sizeof(float);
+  const int gy = (Cs + FOLD_CG - 1) / FOLD_CG;
+  const int tiles = (N + 15) / 16;
+  const int n_rounds = (tiles + F16_WPB - 1) / F16_WPB;
+  const int per_cu = std::max(1, std::min(2, (int)((160 * 1024) / lds)));
+  const int gx = std::max(1, std::min(n_rounds, 256 * per_cu / gy));
+  TLT_LAUNCH((k_folded16<S, NTN>), dim3(gx, gy), dim3(F16_WPB * 64), lds, st, (const h16x8 *)P16, lgf,
+             cscg, C, N, inv_sp, B);
+  return hipGetLastError();
+}
+
+template <int S>
+static hipError_t folded16_nt(int ntn, const void *P16, const h16x8 *lgf, const float *cscg, int Cs,
+                              int C, int N, float inv_sp, float *B, hipStream_t st) {
+  switch (ntn) {
+    case 1: return folded16_go<S, 1>(P16, lgf, cscg, Cs, C, N, inv_sp, B, st);
+    case 2: return folded16_go<S, 2>(P16, lgf, cscg, Cs, C, N, inv_sp, B, st);
+    case 3: return folded16_go<S, 3>(P16, lgf, cscg, Cs, C, N, inv_sp, B, st);
+    default: return folded16_go<S, 4>(P16, lgf, cscg, Cs, C, N, inv_sp, B, st);
+  }
+}
+
+// scratch of the FP16 form: fragments [gy][S][NTN][2][64] (16 bytes each,
+// NTN = 4 at most) and column scales [gy][64]
+static size_t fold16_scratch(int K, int Psh, int Cs) {
+  const int S = (K * Psh + 31) / 32, gy = (Cs + FOLD_CG - 1) / FOLD_CG;
+  return (size_t)gy * S * 4 * 128 * 16 + (size_t)gy * 64 * sizeof(float);
+}
+
+static hipError_t launch_folded16(const void *P16, const float *gcol, const float *sh, Cols cols,
+                                  int K, int Psh, int n_sh, int Cs, int N, float inv_sp, float *B,
+                                  void *scratch, hipStream_t st) {
+  const int C = cols.C, J = K * Psh, S = (J + 31) / 32;
+  const int ntn = (std::min(FOLD_CG, C) + 15) / 16;
+  const int gy = (Cs + FOLD_CG - 1) / FOLD_CG;
+  if (S < 1 || S > FOLD16_MAX_STEPS) return hipErrorInvalidValue;
+  h16x8 *lgf = (h16x8 *)scratch;
+  float *cscg = (float *)((char *)scratch + (size_t)gy * S * 4 * 128 * 16);
+  const int slots = gy * S * ntn * 64;
+  TLT_LAUNCH(k_fold_lg16, dim3((slots + 255) / 256), dim3(256), 0, st, gcol, Cs, sh, cols, K, Psh, n_sh,
+             S, ntn, gy, lgf, cscg);
+  switch (S) {
+#define F16S(s) case s: return folded16_nt<s>(ntn, P16, lgf, cscg, Cs, C, N, inv_sp, B, st);
+    F16S(1) F16S(2) F16S(3) F16S(4) F16S(5) F16S(6) F16S(7) F16S(8)
+    F16S(9) F16S(10) F16S(11) F16S(12) F16S(13) F16S(14) F16S(15) F16S(16)
+#undef F16S
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
                          const void *sh, Cols cols, int N, void *B, bool fp64,
-                         void *scratch, hipStream_t st) {
+                         void *scratch, hipStream_t st, const void *P16, float p16_inv) {
   if (Psh > 64 || Cs % 16 != 0) return hipErrorInvalidValue;
   const int nw = K * Psh * Cs;
   const int tiles = (N + 15) / 16;
   const dim3 gx(1, (Cs + FOLD_CG - 1) / FOLD_CG);
   hipError_t e;
-  if (fp64) {
+  if (P16 != nullptr) {
+    if (fp64) return hipErrorInvalidValue;
+    e = launch_folded16(P16, (const float *)gcol, (const float *)sh, cols, K, Psh, n_sh, Cs, N, p16_inv,
+                        (float *)B, scratch, st);
+  } else if (fp64) {
     TLT_LAUNCH(k_fold_weights<double>, dim3((nw + 255) / 256), dim3(256), 0, st,
                (const double *)gcol, Cs, (const double *)sh, cols, K, Psh, n_sh, (double *)scratch);
     e = folded_go<double>(cols.C, Cs, gx, tiles, st, (const double *)P, Psh, K,

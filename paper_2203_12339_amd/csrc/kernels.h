@@ -141,10 +141,21 @@ hipError_t launch_combine(const void *V, int Cs, const void *gcol, int K, int N,
 
 // Folded lighting transport: B = sum_k g_k P_k L (P_k = W_k H (A o T), stored
 // [N][K][Psh], vertices in original order).
+// With P16 (float32 compute only) the product runs on the FP16 copy of P
+// written by launch_fold_pack, whose scale 1/sp is p16_inv.
 hipError_t launch_folded(const void *P, int Psh, int n_sh, int K, const void *gcol, int Cs,
                          const void *sh, Cols cols, int N, void *B, bool fp64, void *scratch,
-                         hipStream_t st);
+                         hipStream_t st, const void *P16 = nullptr, float p16_inv = 0.f);
 size_t folded_scratch_bytes(int K, int Psh, int Cs, bool fp64);
+// FP16 copy of P for the folded product: J = K Psh contraction indices in
+// S = ceil(J / 32) steps of 32, one 1 KB A-operand fragment per (16-row
+// tile, step); largest J it takes (0 if none).
+constexpr int FOLD16_MAX_STEPS = 16;
+size_t fold16_bytes(int N, int J);
+// largest |P| (float bits) into *absmax (a device word the caller zeroed)
+hipError_t launch_fold_absmax(const float *P, int64_t n, unsigned *absmax, hipStream_t st);
+// P16 = sp * P in fragment order (sp a power of two)
+hipError_t launch_fold_pack(const float *P, int N, int J, float sp, void *P16, hipStream_t st);
 
 // Adjoint from Z_k = P_k^T dB: partial rows, then the final reduction.
 // `partial` holds adjoint_partial_bytes(N, K, n_sh, C, fp64) bytes.

@@ -137,13 +137,14 @@ EXPORTED = ["tlt_prepare_scene", "tlt_build_rows", "tlt_create", "tlt_destroy", 
 TUNE_TILE_CHUNK, TUNE_STREAM_WAVES_PER_CU, TUNE_STREAM_EPL, TUNE_STREAM_NT = 1, 2, 3, 4
 TUNE_SPATIAL_LANES, TUNE_SPATIAL_UNROLL, TUNE_SPATIAL_SYNTH_LANES, TUNE_SPATIAL_SEGMENT = 5, 6, 7, 8
 TUNE_TILE_SHAPE, TUNE_IRRADIANCE_HAAR, TUNE_BF16_HEAD, TUNE_TILE_SPARSE = 9, 10, 11, 12
+TUNE_FOLDED_FP32 = 13
 TUNING_KEYS = {"tile_chunk": TUNE_TILE_CHUNK, "stream_waves_per_cu": TUNE_STREAM_WAVES_PER_CU,
                "stream_epl": TUNE_STREAM_EPL, "stream_nt": TUNE_STREAM_NT,
                "spatial_lanes": TUNE_SPATIAL_LANES, "spatial_unroll": TUNE_SPATIAL_UNROLL,
                "spatial_synth_lanes": TUNE_SPATIAL_SYNTH_LANES,
                "spatial_segment": TUNE_SPATIAL_SEGMENT, "tile_shape": TUNE_TILE_SHAPE,
                "irradiance_haar": TUNE_IRRADIANCE_HAAR, "bf16_head": TUNE_BF16_HEAD,
-               "tile_sparse": TUNE_TILE_SPARSE}
+               "tile_sparse": TUNE_TILE_SPARSE, "folded_fp32": TUNE_FOLDED_FP32}
 
 
 class TltError(RuntimeError):
