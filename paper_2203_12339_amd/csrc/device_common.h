@@ -7,6 +7,7 @@
 
 #include <hip/hip_ext.h>
 
+#include "index_maps.h"
 #include "kernels.h"
 
 // Kernel launch that carries the profiled stage's timing events, if any.

@@ -279,9 +279,10 @@ __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__res
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
 #pragma unroll
-      for (int g = 0; g < G4; ++g) x4[r][g] = *reinterpret_cast<const float4 *>(prow[r] + koff + 16 * g + 4 * lk);
+      for (int g = 0; g < G4; ++g)
+        x4[r][g] = *reinterpret_cast<const float4 *>(prow[r] + koff + idx::fold_group_index(g, lk, 0));
 #pragma unroll
-      for (int q = 0; q < R4; ++q) x1[r][q] = prow[r][koff + 16 * G4 + 4 * q + lk];
+      for (int q = 0; q < R4; ++q) x1[r][q] = prow[r][koff + idx::fold_tail_index(G4, q, lk)];
     }
   };
   // the B operands of a whole term are read from LDS before its matrix work
@@ -293,11 +294,13 @@ __global__ __launch_bounds__(FOLD_WPB * 64) void k_folded_lds(const float *__res
 #pragma unroll
       for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int nt = 0; nt < NTN; ++nt) bv[4 * g + v][nt] = lk_rows[(16 * g + 4 * lk + v) * FOLD_LDW + nt * 16];
+        for (int nt = 0; nt < NTN; ++nt)
+          bv[4 * g + v][nt] = lk_rows[idx::fold_group_index(g, lk, v) * FOLD_LDW + nt * 16];
 #pragma unroll
     for (int q = 0; q < R4; ++q)
 #pragma unroll
-      for (int nt = 0; nt < NTN; ++nt) bv[4 * G4 + q][nt] = lk_rows[(16 * G4 + 4 * q + lk) * FOLD_LDW + nt * 16];
+      for (int nt = 0; nt < NTN; ++nt)
+        bv[4 * G4 + q][nt] = lk_rows[idx::fold_tail_index(G4, q, lk) * FOLD_LDW + nt * 16];
 #pragma unroll
     for (int g = 0; g < G4; ++g)
 #pragma unroll

@@ -221,7 +221,7 @@ __device__ void haar_chunk(const PrepArgs &a, CT *x, int chunk, int c0, CT *ehat
 #pragma unroll
     for (int p = 0; p < n / 2; ++p) {
       const CT lo = v[2 * p], hi = v[2 * p + 1];
-      const int64_t j = (int64_t)half * (a.n_chunks + chunk) + g * (n / 2) + p;
+      const int64_t j = idx::haar_row(half, a.n_chunks, chunk, idx::haar_reg_detail(g, n, p));
       store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (lo - hi) * h);
       v[p] = (lo + hi) * h;
     }
@@ -239,7 +239,7 @@ __device__ void haar_chunk(const PrepArgs &a, CT *x, int chunk, int c0, CT *ehat
 #pragma unroll
     for (int p = 0; p < n / 2; ++p) {
       const CT lo = u[2 * p], hi = u[2 * p + 1];
-      const int64_t j = (int64_t)half * (a.n_chunks + chunk) + p;
+      const int64_t j = idx::haar_row(half, a.n_chunks, chunk, p);
       store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (lo - hi) * h);
       u[p] = (lo + hi) * h;
     }
@@ -391,7 +391,7 @@ __device__ void tl_block(const PrepArgs &a, int t, unsigned char *smem) {
         const int i = idx >> 4, cc = idx & 15;
         const CT p = x[(2 * i) * TL_STRIDE + cc];
         const CT q = x[(2 * i + 1) * TL_STRIDE + cc];
-        const int64_t j = (int64_t)half * (a.n_chunks + chunk) + i;
+        const int64_t j = idx::haar_row(half, a.n_chunks, chunk, i);
         store_e(ehat, ehat2, a.split, (size_t)j * a.Cs + c0 + cc, (p - q) * h);
         sv[u] = (p + q) * h;
       }
@@ -430,7 +430,8 @@ __global__ __launch_bounds__(256) void k_haar_top(const CT *__restrict__ partial
     const int half = len >> 1;
     for (int i = threadIdx.x; i < half; i += 256) {
       const CT p = src[2 * i], q = src[2 * i + 1];
-      store_e(ehat, ehat2, split, (size_t)(half + i) * Cs + c, (p - q) * h);
+      // the levels above the chunks run as one chunk of n_chunks values
+      store_e(ehat, ehat2, split, (size_t)idx::haar_row(half, 1, 0, i) * Cs + c, (p - q) * h);
       dst[i] = (p + q) * h;
     }
     __syncthreads();

@@ -133,11 +133,10 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
   // blocks, and the column groups of one block occupy consecutive slots of
   // the same XCD, so they run together and share the W block through L2.
   const int ng = a.n_groups;
-  const int per_xcd = (a.n_blocks + 7) / 8;
-  const int slot = blockIdx.x >> 3;
-  const int b = (blockIdx.x & 7) * per_xcd + slot / ng;
-  const int grp = slot % ng;
-  if (slot / ng >= per_xcd || b >= a.n_blocks) return;
+  const int per_xcd = idx::tile_per_xcd(a.n_blocks);
+  const int b = idx::tile_block(blockIdx.x, per_xcd, ng);
+  const int grp = idx::tile_group(blockIdx.x, ng);
+  if (!idx::tile_runs(blockIdx.x, per_xcd, ng, a.n_blocks)) return;
   const int lane = threadIdx.x & 63;
   // waves split the m-tiles; the sparse form branches on the wave's m-tiles,
   // so its wave index is made a scalar
@@ -187,8 +186,8 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       // fragment base, lane slot of the first of the item's four columns,
       // and the slot swizzle of this (column tile, lane group): see read_b
       it_lds[it] = (sl * NT + n / 16) * H * 64 * KPL;
-      it_slot[it] = lg * 16 + (n % 16);
-      it_sw[it] = (n / 16 + NT * lg) & 3;
+      it_slot[it] = idx::tile_stage_lane(n, lg);
+      it_sw[it] = idx::tile_swizzle(n / 16, lg, NT);
     }
   }
   __syncthreads();  // union ids visible
@@ -226,7 +225,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
               hw[i] = __builtin_amdgcn_perm(w1, w0, 0x05040100u);
               lw[i] = __builtin_amdgcn_perm(w1, w0, 0x07060302u);
             }
-            const int ph = ((it_slot[it] + jj) ^ it_sw[it]) * KPL;
+            const int ph = idx::tile_stage_slot(it_slot[it], jj, it_sw[it]) * KPL;
             *reinterpret_cast<BFrag *>(stage + it_lds[it] + ph) = __builtin_bit_cast(BFrag, hw);
             *reinterpret_cast<BFrag *>(stage + it_lds[it] + ph + 64 * KPL) =
                 __builtin_bit_cast(BFrag, lw);
@@ -315,7 +314,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
           const float v = stage[((size_t)sl * 4 + (lane >> 4)) * CGS + min(n, cg - 1)];
           dst[nt][h] = n < cg ? v : 0.f;
         } else {
-          const int slot = lane ^ ((nt + NT * (lane >> 4)) & 3);
+          const int slot = idx::tile_read_slot(lane, nt, NT);
           dst[nt][h] = *reinterpret_cast<const BFrag *>(
               stage + ((size_t)((sl * NT + nt) * H + h) * 64 + slot) * KPL);
         }

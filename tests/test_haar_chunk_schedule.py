@@ -1,16 +1,24 @@
 """The irradiance kernel runs the Haar levels of a chunk in a different
 schedule from the plain level-by-level loop (thread-local levels first, one
 exchange, then the last four levels).  This emulates both schedules in
-float32 with the kernel's index arithmetic and checks that they write the
-same coefficient to the same row, bit for bit, for every chunk length the
-kernel uses, and that the result is the orthonormal Haar transform."""
+float32 -- the register schedule with the kernel's own row functions
+(haar_row, haar_reg_detail in csrc/index_maps.h, compiled for the host),
+the plain loop with rows from the global coefficient order -- and checks
+that they write the same coefficient to the same row, bit for bit, for
+every chunk length the kernel uses, and that the result is the orthonormal
+Haar transform."""
 import numpy as np
 import pytest
+
+from _index_maps import lib
 
 H = np.float32(0.70710678118654752440)
 
 
 def level_by_level(x, n_chunks, chunk):
+    """Rows in the global order of the transform of all n_chunks chunks:
+    the level with `half` details per chunk holds n_chunks * half details
+    at rows n_chunks * half .. 2 n_chunks * half - 1, chunk by chunk."""
     out = {}
     x = x.copy()
     ln = x.shape[0]
@@ -18,13 +26,14 @@ def level_by_level(x, n_chunks, chunk):
         half = ln // 2
         p, q = x[0:ln:2], x[1:ln:2]
         for i in range(half):
-            out[half * (n_chunks + chunk) + i] = (p[i] - q[i]) * H
+            out[n_chunks * half + chunk * half + i] = (p[i] - q[i]) * H
         x[:half] = (p + q) * H
         ln = half
     return out, x[0]
 
 
 def register_schedule(x, n_chunks, chunk):
+    L = lib()
     ch_rows = x.shape[0]
     R = ch_rows // 16
     out = {}
@@ -36,7 +45,7 @@ def register_schedule(x, n_chunks, chunk):
         while n > 1:
             for p in range(n // 2):
                 lo, hi = v[2 * p], v[2 * p + 1]
-                out[half * (n_chunks + chunk) + g * (n // 2) + p] = (lo - hi) * H
+                out[L.haar_row(half, n_chunks, chunk, L.haar_reg_detail(g, n, p))] = (lo - hi) * H
                 v[p] = (lo + hi) * H
             half //= 2
             n //= 2
@@ -47,11 +56,22 @@ def register_schedule(x, n_chunks, chunk):
     while n > 1:
         for p in range(n // 2):
             lo, hi = u[2 * p], u[2 * p + 1]
-            out[half * (n_chunks + chunk) + p] = (lo - hi) * H
+            out[L.haar_row(half, n_chunks, chunk, p)] = (lo - hi) * H
             u[p] = (lo + hi) * H
         half //= 2
         n //= 2
     return out, u[0]
+
+
+@pytest.mark.parametrize("n_chunks", [1, 2, 64, 1024])
+def test_top_levels_follow_the_global_order(n_chunks):
+    """The levels above the chunks (one chunk of n_chunks sums): detail i
+    of the level with `half` details is row half + i."""
+    L = lib()
+    half = n_chunks // 2
+    while half >= 1:
+        assert [L.haar_row(half, 1, 0, i) for i in range(half)] == list(range(half, 2 * half))
+        half //= 2
 
 
 @pytest.mark.parametrize("ch_rows", [16, 32, 64, 128, 256])

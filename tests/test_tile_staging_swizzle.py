@@ -1,19 +1,22 @@
-"""LDS layout of the staged irradiance in the 16-bit tile kernel, emulated
-on the host with the kernel's index arithmetic: B-operand fragments hold
-lane l's 16 bytes at slot l ^ ((tile + NT (l / 16)) & 3); a quarter-wave of
-a fragment read then covers all 16 sixteen-byte bank groups, and the
-staging stores of 16 consecutive work items land in 16 different groups."""
+"""LDS layout of the staged irradiance in the 16-bit tile kernel, with the
+kernel's own index functions (tile_swizzle, tile_read_slot,
+tile_stage_lane, tile_stage_slot in csrc/index_maps.h, compiled for the
+host): B-operand fragments hold lane l's 16 bytes at slot
+l ^ ((tile + NT (l / 16)) & 3); a quarter-wave of a fragment read then
+covers all 16 sixteen-byte bank groups, and the staging stores of 16
+consecutive work items land in 16 different groups."""
 import pytest
+
+from _index_maps import lib
 
 KPL, H = 8, 2          # 16-bit values per lane and operand; hi and lo halves
 
 
-def read_slot(lane, nt, NT):
-    return lane ^ ((nt + NT * (lane >> 4)) & 3)
-
-
 def store_groups(NT, jj, items):
-    """16-byte bank group of each item's store number jj (hi half)."""
+    """16-byte bank group of each item's store number jj (hi half); the
+    item decomposition is the staging loop's (column quad q, lane group lg,
+    step sl)."""
+    L = lib()
     cq = NT * 16 // 4                      # column quads per (step, lane group)
     groups = []
     for item in items:
@@ -22,17 +25,16 @@ def store_groups(NT, jj, items):
         sl = item // (cq * 4)
         n = 4 * q
         base = (sl * NT + n // 16) * H * 64 * KPL      # fragment base (elements)
-        slot = lg * 16 + n % 16
-        sw = (n // 16 + NT * lg) & 3
-        ph = ((slot + jj) ^ sw) * KPL
+        ph = L.tile_stage_slot(L.tile_stage_lane(n, lg), jj, L.tile_swizzle(n // 16, lg, NT)) * KPL
         groups.append((2 * (base + ph) // 16) % 16)
     return groups
 
 
 @pytest.mark.parametrize("NT", [1, 2, 3, 4])
 def test_fragment_reads_cover_all_bank_groups(NT):
+    L = lib()
     for nt in range(NT):
-        slots = [read_slot(l, nt, NT) for l in range(64)]
+        slots = [L.tile_read_slot(l, nt, NT) for l in range(64)]
         assert sorted(slots) == list(range(64))          # a permutation of the lanes
         for quarter in range(4):
             qs = slots[16 * quarter:16 * quarter + 16]
@@ -51,12 +53,10 @@ def test_staging_stores_spread_over_bank_groups(NT):
 def test_store_and_read_agree_on_slots(NT):
     """Column n of lane group lg is written where the read of its column
     tile expects lane lg * 16 + n % 16."""
+    L = lib()
     for lg in range(4):
         for n in range(0, NT * 16):
             nt = n // 16
-            lane = lg * 16 + n % 16
-            q0 = (n // 4) * 4
-            slot = lg * 16 + q0 % 16
-            sw = (q0 // 16 + NT * lg) & 3
-            written = (slot + (n - q0)) ^ sw
-            assert written == read_slot(lane, nt, NT)
+            q0 = (n // 4) * 4                            # the item's column quad
+            written = L.tile_stage_slot(L.tile_stage_lane(q0, lg), n - q0, L.tile_swizzle(q0 // 16, lg, NT))
+            assert written == L.tile_read_slot(lg * 16 + n % 16, nt, NT)
