@@ -41,7 +41,8 @@ def log(*a):
 # sources that fix the transport kernel, its launch shape and the layout of
 # the data it reads (kept rows, tiles, irradiance coefficients)
 TRANSPORT_SOURCES = ("csrc/k_tiles.hip", "csrc/k_build.hip", "csrc/k_prep.hip",
-                     "csrc/device_common.h", "csrc/kernels.h", "csrc/api.hip", "tuning.json")
+                     "csrc/device_common.h", "csrc/index_maps.h", "csrc/kernels.h", "csrc/api.hip",
+                     "tuning.json")
 
 
 def kernel_hash():
