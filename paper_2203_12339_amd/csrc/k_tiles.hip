@@ -338,6 +338,15 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     const int ns_next = min(CS, n_steps - nxt);
     if (ns_next > 0) gather(nxt, ns_next);
     if (s0 > 0) mask_window(s0);
+    // sparse blocks: the B operands of a step are read one step ahead, into
+    // two buffers taken in turn by step parity (compile-time indices; at
+    // large-f16-163842 1474 -> 1455 us).  Dense blocks read them at their
+    // step: the extra registers cost their 128-row launches occupancy
+    // (batch64-bf16-40962: 570 -> 672 us).
+    BFrag bfs[2][NT][H];
+    if constexpr (SP) {
+      if (((win(0) >> tbase) & ((1u << MTW) - 1u)) != 0u) read_b(0, bfs[0]);
+    }
     // Groups of PD steps: a group runs whole or not at all, so the W ring
     // stays in step (one refill per step, in step order) and the load
     // counters can be waited on exactly.  A step whose mask has none of the
@@ -360,11 +369,12 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
         for (int p = 0; p < PD; ++p) {
           const int sl = g0 + p;
           if constexpr (SP) {
-            // scalar: this wave's m-tiles stored at this step
+            // scalar: this wave's m-tiles stored at this step and the next
             const uint32_t wb = (win(sl) >> tbase) & ((1u << MTW) - 1u);
+            const uint32_t wbn = sl + 1 < CS ? (win(sl + 1) >> tbase) & ((1u << MTW) - 1u) : 0u;
+            if (wbn != 0u) read_b(sl + 1, bfs[(sl + 1) & 1]);   // then sl + 1 < ns
             if (wb != 0u) {   // then sl < ns
-              BFrag bf[NT][H];
-              read_b(sl, bf);
+              BFrag (&bf)[NT][H] = bfs[sl & 1];
               if (wb == (1u << MTW) - 1u) {
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
