@@ -892,8 +892,7 @@ tlt_status device_build_tiles(tlt_ctx *c, int tV, int n_cols) {
   if ((s = dalloc(c, (void **)&c->t_foff, sizeof(int64_t) * (nb + 1), "tile fragment offsets")) != TLT_OK) goto out;
   if ((s = dalloc(c, (void **)&c->t_ucol, sizeof(int32_t) * (size_t)ho[nb], "tile columns")) != TLT_OK) goto out;
   if ((s = dalloc(c, (void **)&c->t_mask, sizeof(uint16_t) * (size_t)(ho[nb] / a.kstep), "tile masks")) != TLT_OK) goto out;
-  // dense blocks: zeroed slack after the last block, read by its W ring
-  val_alloc = c->t_val_bytes + (a.order ? 0 : TILE_VAL_SLACK);
+  val_alloc = c->t_val_bytes;
   if ((s = dalloc(c, &c->t_val, val_alloc, "tile values")) != TLT_OK) goto out;
   BTRY(hipMemcpy(c->t_off, ho.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));
   BTRY(hipMemcpy(c->t_foff, fo.data(), sizeof(int64_t) * (nb + 1), hipMemcpyHostToDevice));

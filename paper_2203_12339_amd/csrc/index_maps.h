@@ -37,16 +37,25 @@ TLT_HD bool tile_runs(unsigned h, int per_xcd, int ng, int n_blocks) {
 
 // ---- staged irradiance of the 16-bit tiles ----
 // The B-operand fragment of (step, column tile nt, half) holds lane l's 16
-// bytes at slot l ^ tile_swizzle(nt, l / 16, NT).  The swizzle permutes
-// slots inside groups of four only, so a quarter-wave read still covers
-// the 16 sixteen-byte bank groups, while the staging stores of consecutive
-// items spread over all of them.
-TLT_HD int tile_swizzle(int nt, int lane_group, int NT) { return (nt + NT * lane_group) & 3; }
-TLT_HD int tile_read_slot(int lane, int nt, int NT) { return lane ^ tile_swizzle(nt, lane >> 4, NT); }
+// bytes at slot l ^ tile_swizzle(nt, l / 16, bit 3 of l).  The swizzle
+// permutes slots inside groups of four only (so a fragment read stays one
+// contiguous 1 KB).  The LDS serves 16-byte accesses eight lanes at a time
+// over 32 four-byte banks (measured: with the earlier swizzle (nt + NT lg)
+// mod 4, built for sixteen lanes over 64 banks, the reads had no bank
+// conflicts and the staging stores 28 M conflict cycles per launch at
+// batch64-bf16-40962); this one puts every group of eight consecutive lanes
+// of a read, and of a staging store of eight consecutive items, on eight
+// distinct 16-byte units modulo 8, for one to four column tiles per group.
+TLT_HD int tile_swizzle(int nt, int lane_group, int col_hi) {
+  return (col_hi ^ ((nt & 1) << 1) ^ ((nt >> 1) & 1) ^ (3 * (lane_group & 1)) ^ ((lane_group >> 1) & 1)) & 3;
+}
+TLT_HD int tile_read_slot(int lane, int nt) { return lane ^ tile_swizzle(nt, lane >> 4, (lane >> 3) & 1); }
 // Staging item (column quad starting at column n of the group, lane group
-// lg): the lane of its first column, and the slot its column n + jj is
-// stored at (jj = 0..3).
+// lg): the lane of its first column, the swizzle of its four slots (the
+// quad lies in one half of a 16-column tile), and the slot its column
+// n + jj is stored at (jj = 0..3).
 TLT_HD int tile_stage_lane(int n, int lg) { return lg * 16 + n % 16; }
+TLT_HD int tile_stage_swizzle(int n, int lg) { return tile_swizzle(n / 16, lg, (n % 16) >> 3); }
 TLT_HD int tile_stage_slot(int stage_lane, int jj, int sw) { return (stage_lane + jj) ^ sw; }
 
 // ---- float32 folded product (k_folded_lds) ----

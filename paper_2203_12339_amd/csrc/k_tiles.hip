@@ -187,7 +187,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       // and the slot swizzle of this (column tile, lane group): see read_b
       it_lds[it] = (sl * NT + n / 16) * H * 64 * KPL;
       it_slot[it] = idx::tile_stage_lane(n, lg);
-      it_sw[it] = idx::tile_swizzle(n / 16, lg, NT);
+      it_sw[it] = idx::tile_stage_swizzle(n, lg);
     }
   }
   __syncthreads();  // union ids visible
@@ -286,24 +286,23 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
       fp_load += (uint32_t)__popc(ms);
     } else {
       // every fragment stored: (s, t) is number s MT + t.  The step is a
-      // scalar offset, the lane a fixed vector offset; the ring reads up to
-      // 2 PD - 1 steps past the block's end, which only ever multiply zero B
-      // fragments and read finite values: the next block's, or after the
-      // last block the zeroed slack allocated behind the tile values.
+      // scalar offset, the lane a fixed vector offset.  Steps past the
+      // block's end (the ring runs up to CS + PD - 1 of them ahead) reload
+      // its last step: they only ever multiply zero B fragments, and every
+      // read stays inside the block.
+      const int sc = min(s_load, n_steps - 1);
 #pragma unroll
       for (int m = 0; m < MTW; ++m)
-        dst[m] = TK::template frag<WAUX>(wrs, (tbase + m) * FRAG + lane_off, s_load * MT * FRAG);
+        dst[m] = TK::template frag<WAUX>(wrs, (tbase + m) * FRAG + lane_off, sc * MT * FRAG);
     }
     ++s_load;
   };
   // B fragments of step sl of the staged chunk (unconditional LDS reads).
   // 16-bit kinds: the fragment of (step, column tile nt, half h) holds lane
-  // l's 16 bytes at slot l ^ ((nt + NT (l / 16)) & 3).  The swizzle only
-  // permutes slots inside a group of four, so a quarter-wave still reads 16
-  // distinct 16-byte bank groups, and the staging writes -- each thread
-  // writes one column quad (four consecutive slots, one store each) for
-  // consecutive (column tile, lane group) pairs -- now spread a store
-  // instruction over all 16 bank groups instead of 4 of them.
+  // l's 16 bytes at slot idx::tile_read_slot(l, nt), a permutation inside
+  // groups of four slots that keeps both these reads and the staging
+  // stores (each thread writes one column quad, four consecutive slots, for
+  // consecutive (column quad, lane group) items) free of bank conflicts.
   auto read_b = [&](int sl, BFrag (&dst)[NT][H]) {
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt)
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
           const float v = stage[((size_t)sl * 4 + (lane >> 4)) * CGS + min(n, cg - 1)];
           dst[nt][h] = n < cg ? v : 0.f;
         } else {
-          const int slot = idx::tile_read_slot(lane, nt, NT);
+          const int slot = idx::tile_read_slot(lane, nt);
           dst[nt][h] = *reinterpret_cast<const BFrag *>(
               stage + ((size_t)((sl * NT + nt) * H + h) * 64 + slot) * KPL);
         }
@@ -349,13 +348,21 @@ __global__ __launch_bounds__(512) void k_tiles(TileArgs a) {
     }
     // Groups of PD steps: a group runs whole or not at all, so the W ring
     // stays in step (one refill per step, in step order) and the load
-    // counters can be waited on exactly.  A step whose mask has none of the
-    // wave's m-tiles (absent fragments, and the steps of the last group past
-    // the block's end, whose mask is 0) skips its operand reads and matrix
-    // work; only its refill runs.
+    // counters can be waited on exactly.  16-bit kinds run every group of a
+    // chunk, also past the block's end in its last chunk (those steps
+    // multiply zero B fragments, or have an empty mask), so the number of
+    // loads issued per chunk is a compile-time constant: the staging of the
+    // next chunk then waits for its gathered rows only, not for the W ring
+    // (with a runtime group count the compiler waited for every load, and
+    // the ring drained at each chunk: batch64-bf16-40962 562 -> 546 us in
+    // one sweep).
+    // Float32 chunks hold up to 256 steps and keep the runtime bound.  A
+    // step whose mask has none of the wave's m-tiles (absent fragments, and
+    // steps past the block's end, whose mask is 0) skips its operand reads
+    // and matrix work; only its refill runs.
 #pragma unroll
     for (int g0 = 0; g0 < CS; g0 += PD) {
-      if (g0 < ns) {
+      if (KIND != 0 || g0 < ns) {
         float bg[KIND == 0 ? PD : 1];
         if constexpr (KIND == 0) {
           const int n = lane & 15;
@@ -526,9 +533,8 @@ static hipError_t tiles_launch(TileArgs a, size_t per_step, hipStream_t st) {
   const size_t lds =
       masks + (a.sparse ? (sizeof(uint16_t) * (size_t)(a.max_union / TileKind<KIND>::KSTEP) + 15) / 16 * 16 : 0);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  // dense blocks: the ring's reach past the last block stays inside the slack
-  const size_t step_bytes = (size_t)(a.R / 16) * 64 * TileKind<KIND>::KPL * TileKind<KIND>::VSZ;
-  if (!a.sparse && (size_t)(2 * PD - 1) * step_bytes > TILE_VAL_SLACK) return hipErrorInvalidValue;
+  // (dense blocks clamp the ring's step to the block's last one, so every
+  // W read stays inside the block)
   const int hw = 8 * ((a.n_blocks + 7) / 8) * a.n_groups;
   const bool nt_w = a.n_groups == 1 && a.stream_w;
   if constexpr (KIND == 0) {

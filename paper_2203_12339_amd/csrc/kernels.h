@@ -124,11 +124,6 @@ hipError_t launch_tiles(const TileArgs &a, int vdt, hipStream_t st);
 int tile_kstep(int vdt);
 // Largest block (rows V*K) the tile kernel takes for a storage type.
 int tile_max_rows(int vdt);
-// Zeroed bytes allocated after dense tile values: the W register ring of the
-// last block reads up to 2*PD - 1 steps (at most 62 KB) past its end.
-// launch_tiles refuses a shape whose ring would reach further.  (Sparse
-// blocks address every fragment through the range-checked offset.)
-constexpr size_t TILE_VAL_SLACK = 128 * 1024;
 
 // Outgoing Fresnel factor (1/pi) F_t(eta, w_o) applied to B in place.
 hipError_t launch_view(void *B, const void *cosv, const double *theta, Cols cols, int N,
