@@ -27,7 +27,7 @@ _SCENE = None
 _INPUT = None
 
 
-def _work(job):
+def _run_job(job):
     from oracle import adjoint
     kind, idx = job
     L, th, rows, bb = _INPUT
@@ -59,8 +59,8 @@ def _child(inp, out):
     splits = [c for c in np.array_split(np.arange(len(rows)), 4 * n) if len(c)]
     kept = [c for c in np.array_split(np.arange(n_kept), n) if len(c)]
     with mp.get_context("fork").Pool(n) as pool:
-        res = pool.map(_work, [("rows", c) for c in splits])
-        kc = pool.map(_work, [("kept", c) for c in kept])
+        res = pool.map(_run_job, [("rows", c) for c in splits])
+        kc = pool.map(_run_job, [("kept", c) for c in kept])
     d = {"ref": np.concatenate([r[0] for r in res], axis=1)}
     if bb is not None:
         d["gL"] = sum(r[1] for r in res)
